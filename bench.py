@@ -1,0 +1,196 @@
+"""Benchmark: sliced contraction of the 53-qubit, 14-cycle synthetic random
+circuit network (6x9 grid with one missing site, 6 open qubits -> bunches of
+64 amplitudes, every per-slice tensor <= 2^32 entries) on one MI355X.
+
+One step = one slice: bind, every pairwise contraction of the slice
+(permutes, complex GEMMs on MFMA, gathered contractions) and the FP64
+accumulation of its 64 amplitudes.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--form auto|4m|3m]
+                  [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sec/slice + complex TFLOP/s (% MFMA peak), 53-qubit 14-cycle synthetic RCS"
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0       # GB/s
+KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 9: "k_accum"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, sub_log2: int):
+    """The oracle on a bounded sample: one sub-slice of slice 0 (extra wires
+    sliced until every tensor has <= 2^sub_log2 entries); rate in complex
+    TFLOP/s of algorithmic work (8 flops per complex multiply-add)."""
+    import oracle
+    from oracle.tn import contract_network, slice_assignment
+    from rqcgen import network_structure, order_stats, slice_to_fit
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    ns = network_structure(w.circuit, w.open_qubits)
+    allsl = slice_to_fit(ns, w.pairs, sub_log2, initial=w.sliced)
+    st = order_stats(ns, w.pairs, allsl)
+    leaves, ow = oracle.build_network(w.circuit, w.open_qubits, w.out_bits)
+    t0 = time.perf_counter()
+    contract_network(leaves, w.pairs, ow, slice_assignment(allsl, 0))
+    dt = time.perf_counter() - t0
+    rate = st.flops_per_slice / dt / 1e12
+    return {"value": rate, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 numpy tensordot contraction of one sub-slice of slice 0 "
+                       f"({len(allsl) - len(w.sliced)} extra sliced wires, tensors <= 2^{sub_log2}, "
+                       f"{st.flops_per_slice:.3e} flop) in {dt:.1f} s"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", default="auto", choices=["auto", "4m", "3m"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sub-log2", type=int, default=26)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the slice range would be split "
+                                   "across GPUs with one final 1 KiB reduction (not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2111_01066_amd import tnrcs
+    from rqcgen.workloads import config3
+
+    w = config3()
+    log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
+    t0 = time.perf_counter()
+    plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, gemm_form=args.form,
+                      use_graph=not args.no_graph)
+    info = plan.info()
+    log(f"[bench] planned in {time.perf_counter() - t0:.2f} s: {info['n_device_steps']} device steps, "
+        f"{info['n_kernels']} kernels/slice, arena {info['arena_bytes'] / 2**30:.1f} GiB, "
+        f"{info['flops_per_slice']:.3e} flop/slice")
+    n_slices = info["n_slices"]
+    K, W = args.steps, args.warmup
+    if K + W > n_slices:
+        K = max(1, n_slices - W)
+    stream = torch.cuda.current_stream()
+    amp = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    for s in range(W):
+        plan.contract(s, s + 1, amp)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup slice {s} done")
+    amp.zero_()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for s in range(K):
+        plan.contract(s, s + 1, amp)
+        if (s + 1) % 4 == 0 or s + 1 == K:
+            log(f"[bench] timed slice {s} enqueued")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    flags = plan.status()
+    sec_per_slice = gpu_s / K
+    tflops = info["flops_per_slice"] * K / gpu_s / 1e12
+    log(f"[bench] {K} slices in {gpu_s:.3f} s (wall {wall:.3f} s): {sec_per_slice:.4f} s/slice, "
+        f"{tflops:.2f} complex TFLOP/s, flags={flags}")
+
+    # per-kernel durations of one slice (HIP events on the launch stream)
+    ops = plan.json()["ops"]
+    scratch = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    ms = plan.profile(0, scratch)
+    kinds = [o["kind"] for o in ops] + [9]
+    flops = [o["flops"] for o in ops] + [0.0]
+    byts = [o["bytes"] for o in ops] + [64 * 8.0]
+    by_kind = {}
+    for k, t, f, b in zip(kinds, ms, flops, byts):
+        d = by_kind.setdefault(k, {"ms": 0.0, "n": 0, "flops": 0.0, "bytes": 0.0})
+        d["ms"] += float(t)
+        d["n"] += 1
+        d["flops"] += f
+        d["bytes"] += b
+    dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
+    d = by_kind[dom]
+    avg_ms = d["ms"] / d["n"]
+    if dom == 1:
+        achieved = d["flops"] / d["n"] / (avg_ms / 1e3) / 1e12
+        roof = {"kernel": KIND_NAMES[dom], "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                "launches_per_slice": d["n"], "avg_ms": avg_ms,
+                "flop_per_launch": d["flops"] / d["n"]}
+    else:
+        achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
+        roof = {"kernel": KIND_NAMES[dom], "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None, "launches_per_slice": d["n"], "avg_ms": avg_ms,
+                "bytes_per_launch": d["bytes"] / d["n"]}
+    perm = by_kind.get(0)
+    kernel_split = {KIND_NAMES[k]: {"ms_per_slice": v["ms"], "launches": v["n"]} for k, v in by_kind.items()}
+    if perm and perm["ms"] > 0:
+        kernel_split["k_permute"]["GB/s"] = perm["bytes"] / (perm["ms"] / 1e3) / 1e9
+        kernel_split["k_permute"]["frac_hbm"] = kernel_split["k_permute"]["GB/s"] / PEAK_HBM
+    log(f"[bench] per-kernel: {json.dumps(kernel_split)}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(w, args.cpu_sub_log2)
+        log(f"[bench] oracle: {cpu['value']:.4f} TFLOP/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+
+    out = {
+        "metric": METRIC,
+        "value": tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": sec_per_slice * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "rqc-53q-6x9m1-d14: 53 qubits (6x9 grid, 1 seeded-missing site), 14 cycles, "
+                        "6 open qubits (64-amplitude bunch), per-slice tensors <= 2^32 entries",
+            "sec_per_slice": sec_per_slice,
+            "complex_tflops": tflops,
+            "frac_fp32_mfma_peak": tflops / PEAK_FP32_MFMA,
+            "n_slices_total": n_slices,
+            "extrapolated_total_s": sec_per_slice * n_slices,
+            "flops_per_slice": info["flops_per_slice"],
+            "bytes_per_slice": info["bytes_per_slice"],
+            "gemm_form": args.form,
+            "graph": not args.no_graph,
+            "kernels_per_slice": info["n_kernels"],
+            "kernel_split": kernel_split,
+            "numeric_flags": flags,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * tnrcs.h - C ABI of the MI355X (gfx950) sliced tensor-network contraction
+ * library for random-quantum-circuit amplitudes.
+ *
+ * What is computed.  For a circuit U = G_m ... G_1 on n qubits, a set O of
+ * open qubits and bit values x_C on the closed qubits, the library returns the
+ * bunch of amplitudes a[y] = <x_C, y_O | U | 0^n> for all y in {0,1}^|O|
+ * (main text, "Establishing quantum supremacy baseline": leaving qubits open
+ * yields a correlated bunch at little extra cost).  The amplitude is the
+ * contraction of the circuit's tensor network (main text, section on the
+ * customized TNC algorithm; Supplement Fig. S2), done pairwise in a caller-given
+ * order (Supplement, "Tensor network contraction algorithm": an order is a
+ * list of two-tuples) with a caller-given set of sliced bonds (main text: the
+ * network equals the sum of the smaller networks obtained by fixing the sliced
+ * indices).  Each pairwise contraction is an index permutation followed by a
+ * complex matrix product (Supplement Eq. (matmul)), or the fused form of the
+ * two for skewed shapes (Supplement, CPU-architecture section, Fig. S7a).
+ *
+ * Conventions (all plain data, no ownership transfer unless stated):
+ *  - Qubits 0..n-1.  Bit strings: qubit j is character j; a basis index is
+ *    sum_j x_j 2^(n-1-j).
+ *  - Gate matrices are row-major complex128, re/im interleaved; a two-qubit
+ *    gate acts on |q[0] q[1]> with q[0] the more significant bit.
+ *  - Canonical leaves: ids 0..n-1 are the |0> input vectors; then one leaf per
+ *    gate in circuit order; then one output vector per CLOSED qubit in qubit
+ *    order.  Canonical wires: wire q < n leaves input vector q; every gate
+ *    appends one new wire per entry of its qubit list, in that order.
+ *  - Order (SSA): step t contracts ids order_pairs[2t], order_pairs[2t+1] and
+ *    creates id n_leaves + t; n_steps must be n_leaves - 1 (a full tree).
+ *  - Slice s in [0, 2^k) fixes sliced_wires[j] to bit j of s.
+ *  - Amplitude buffer: complex128 (re, im doubles), 2^|O| entries; entry y
+ *    holds the open qubits (increasing qubit order) as sum_j y_j 2^(|O|-1-j).
+ *
+ * Errors: every function returns TN_OK (0) or a negative TN_E_* code and
+ * never throws; tn_last_error() returns a thread-local message describing the
+ * last failure on the calling thread.
+ */
+#ifndef TNRCS_H
+#define TNRCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TN_OK 0
+#define TN_E_ARG (-1)         /* bad argument (null pointer, range, size) */
+#define TN_E_TOPOLOGY (-2)    /* order is not a full tree / unknown wire */
+#define TN_E_MEM (-3)         /* arena exceeds the budget or device memory */
+#define TN_E_HIP (-4)         /* a HIP runtime call failed */
+#define TN_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+#define TN_E_NUMERIC (-6)     /* non-finite or out-of-range values seen */
+
+#define TN_DTYPE_C64 0   /* complex64 storage, FP32 arithmetic */
+#define TN_DTYPE_F16S 1  /* FP16 storage + per-tensor power-of-two exponent, FP32 accumulation */
+#define TN_DTYPE_BF16S 2 /* BF16 storage + per-tensor power-of-two exponent, FP32 accumulation */
+
+#define TN_GEMM_AUTO 0
+#define TN_GEMM_4M 1 /* Cr = ArBr - AiBi, Ci = ArBi + AiBr: four real products */
+#define TN_GEMM_3M 2 /* three real products: ArBr, AiBi, (Ar+Ai)(Br+Bi) */
+
+/* Numeric status bits reported by tn_plan_status. */
+#define TN_FLAG_NONFINITE 1u  /* a NaN/Inf reached the final tensor */
+#define TN_FLAG_OVERFLOW 2u   /* scaled storage: a value exceeded the format range */
+#define TN_FLAG_UNDERFLOW 4u  /* scaled storage: a tensor's maximum fell below the target range */
+
+typedef struct tn_plan_s* tn_plan_t;
+
+typedef struct {
+  int32_t nq;   /* 1 or 2 */
+  int32_t q[2]; /* qubits; q[1] unused when nq == 1 */
+  double m[32]; /* row-major complex128 matrix, re/im interleaved: 8 doubles (2x2) or 32 (4x4) */
+} tn_gate;
+
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_gates;
+  const tn_gate* gates;    /* n_gates entries, circuit order */
+  const uint8_t* out_bits; /* n_qubits entries (0/1); read only for closed qubits; may be NULL if all open */
+} tn_circuit;
+
+typedef struct {
+  int32_t dtype;          /* TN_DTYPE_* */
+  int32_t gemm_form;      /* TN_GEMM_* */
+  int32_t max_log2;       /* reject plans with a per-slice tensor above 2^max_log2 elements (0: no bound) */
+  int32_t use_graph;      /* 1: run each slice as one replay of a captured HIP graph */
+  int32_t dry_run;        /* 1: plan on the host only; no device calls, no device memory */
+  int32_t device;         /* HIP device ordinal */
+  int32_t host_fold_log2; /* steps whose result has at most 2^host_fold_log2 entries and whose operands
+                             are leaves or folded leaves are evaluated once on the host in FP64 */
+  int32_t reserved;
+  int64_t arena_bytes;    /* device memory budget for intermediates (0: 92% of free memory) */
+} tn_plan_opts;
+
+/* Per-plan totals for one slice (flop convention: one complex multiply-add = 8 flops). */
+typedef struct {
+  int64_t n_slices;        /* 2^k */
+  int32_t n_leaves;        /* canonical leaves */
+  int32_t n_host_steps;    /* steps folded on the host at plan time */
+  int32_t n_device_steps;  /* steps run per slice */
+  int32_t n_kernels;       /* kernel launches per slice */
+  int32_t max_log2;        /* largest per-slice device tensor, log2 elements */
+  int32_t n_open;
+  double flops_per_slice;  /* sum over device steps of 8*M*N*K */
+  double bytes_per_slice;  /* algorithmic bytes: each step reads A and B once and writes C once */
+  double moved_per_slice;  /* bytes the chosen kernels move, extra permute traffic included */
+  int64_t arena_bytes;     /* device arena for intermediates and permute scratch */
+  int64_t leaf_bytes;      /* device leaves (all slices) */
+  int32_t n_dense, n_skinny, n_generic, n_permute; /* kernel-class counts per slice */
+  int32_t k_hist[64];      /* histogram of contracted-index count |K| over device steps */
+} tn_plan_stats;
+
+/* Fills *o with the defaults (complex64, auto GEMM form, graph on, device 0,
+ * host folding up to 2^12 entries, automatic arena budget). */
+void tn_plan_opts_default(tn_plan_opts* o);
+
+/* Plans the contraction (main text TNC section; Supplement Fig. S2 and the
+ * TNC section).  Copies every input.  Validates the circuit, the order (full
+ * SSA tree over the canonical leaves), the sliced wires (in range, distinct,
+ * not open) and the open qubits (distinct, in range); folds small slice-local
+ * subtrees on the host in FP64; chooses tensor layouts and kernels; assigns
+ * device-arena offsets by liveness; unless opts->dry_run, allocates device
+ * memory on opts->device, uploads the leaves and, with use_graph, prepares the
+ * per-slice graph lazily.  opts may be NULL (defaults).  On success *out owns
+ * all of this until tn_plan_destroy. */
+int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps,
+            const int32_t* sliced_wires, int32_t k, const int32_t* open_qubits, int32_t n_open,
+            const tn_plan_opts* opts, tn_plan_t* out);
+
+/* Contracts slices s_begin <= s < s_end and ACCUMULATES (+=) their sum into
+ * amp (device memory, complex128[2^n_open]), in increasing slice order, on
+ * `stream` (a hipStream_t; NULL = the null stream).  Asynchronous: returns
+ * after enqueueing.  The per-slice result is widened to FP64 before it is
+ * added, so the cross-slice sum is FP64 and its order is fixed by the slice
+ * ids; splitting a range over several calls gives the identical sum.  A plan
+ * must be used by one stream at a time.  TN_E_UNSUPPORTED for dry-run plans. */
+int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream);
+
+/* Copies the plan's statistics into *s. */
+int tn_plan_info(tn_plan_t p, tn_plan_stats* s);
+
+/* Writes the plan as JSON (host folds, device leaves, per-step kernels with
+ * layouts and arena offsets) into buf (capacity cap bytes, NUL-terminated);
+ * *needed receives the full length + 1.  buf may be NULL to query the size. */
+int tn_plan_json(tn_plan_t p, char* buf, int64_t cap, int64_t* needed);
+
+/* Copies device leaf i (host-folded, FP64, in its stored layout, all slices)
+ * into out (host memory, 2 * 2^rank doubles).  For tests of the planner. */
+int tn_plan_leaf(tn_plan_t p, int32_t i, double* out, int64_t cap_doubles);
+
+/* Sticky numeric flags (TN_FLAG_*) of the plan's runs so far.  Synchronizes
+ * the stream of the plan's last tn_contract_slices call. */
+int tn_plan_status(tn_plan_t p, uint32_t* flags);
+
+/* Rebinds the closed-qubit output bits without re-planning (re-folds and
+ * re-uploads the affected leaves).  Synchronous. */
+int tn_plan_set_output_bits(tn_plan_t p, const uint8_t* out_bits);
+
+/* Runs slice `slice` once without a graph, accumulating into amp like
+ * tn_contract_slices, with a pair of HIP events on `stream` around every
+ * kernel; synchronizes and writes each kernel's duration in milliseconds to
+ * op_ms[0..n) in plan order (the per-step kernels, then the accumulation).
+ * *n_ops receives the kernel count; cap is op_ms's capacity.  Measurement
+ * support for benchmarks; the slice result is the same as in the graph path. */
+int tn_plan_profile(tn_plan_t p, int64_t slice, void* amp, void* stream, float* op_ms, int32_t cap,
+                    int32_t* n_ops);
+
+/* Releases the plan, its device memory and its graph.  NULL is accepted. */
+int tn_plan_destroy(tn_plan_t p);
+
+const char* tn_last_error(void);
+
+/* ---- standalone kernels of the hot path (same kernels the plans run) ---- */
+
+/* Binary-index tensor permutation (the index permutation of Supplement
+ * Eq. (matmul)): a rank-r tensor with every dimension 2, complex64, row-major
+ * (position p = bit p of the linear index, position 0 fastest).  Output
+ * position q takes input position perm[q]:  out[sum_q b_{perm[q]} 2^q] =
+ * in[sum_p b_p 2^p].  `batch` tensors at strides of 2^r elements.  in/out are
+ * device pointers and must not overlap.  0 <= r <= 40. */
+int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm, int64_t batch,
+                   void* stream);
+
+/* Complex GEMM from real MFMA products with FP32 accumulation:
+ * C[m][n] = sum_k A[m][k] * B[n][k] for `batch` independent problems
+ * (complex64, row-major, A: M x K, B: N x K, C: M x N, batch strides
+ * M*K, N*K, M*N elements).  form = TN_GEMM_4M or TN_GEMM_3M.  M, N multiples
+ * of 64 and K a multiple of 16 (the planner only emits such shapes; other
+ * shapes are routed to the other kernels). */
+int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                 int64_t batch, int32_t form, void* stream);
+
+/* FP64 reductions over an amplitude buffer (complex128, device):
+ *  out[0] = sum |a|^2 over n entries (the norm of an all-open run). */
+int tn_amp_norm2(const void* amp, int64_t n, void* out_dev, void* stream);
+/*  XEB sums over sampled entries: out[0] = sum_i |a[idx_i]|^2,
+ *  out[1] = sum_i |a[idx_i]|^4 (idx: device int64[n_idx]).  F = 2^n out[0]/n_idx - 1. */
+int tn_amp_xeb(const void* amp, int64_t n, const void* idx_dev, int64_t n_idx, void* out_dev,
+               void* stream);
+/*  Histogram of x = scale * |a|^2 into n_bins bins of width xmax/n_bins
+ *  (last bin collects x >= xmax), counts as uint64 (Eq. (fxeb) check). */
+int tn_amp_hist(const void* amp, int64_t n, double scale, double xmax, int32_t n_bins,
+                void* counts_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNRCS_H */

@@ -1,0 +1,430 @@
+// C ABI of the tnrcs library: plan objects, the per-slice scheduler (one HIP
+// graph replay per slice, FP64 accumulation into the caller's buffer) and the
+// standalone kernel entry points.  See include/tnrcs.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace tnrcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return TN_E_HIP;
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t _e = (expr);                 \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+}  // namespace
+
+struct tn_plan_s {
+  PlanCore core;
+  int device = 0;
+  float2* d_leaves = nullptr;
+  float2* d_bound = nullptr;
+  float2* d_arena = nullptr;
+  BindDesc* d_binds = nullptr;
+  Ctrl* d_ctrl = nullptr;
+  int64_t bind_max = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool ran = false;
+};
+
+static const float2* resolve(const tn_plan_s* p, const TRef& r) {
+  switch (r.region) {
+    case kLeaves:
+      return p->d_leaves + r.off;
+    case kBound:
+      return p->d_bound + r.off;
+    default:
+      return p->d_arena + r.off;
+  }
+}
+
+static int upload_leaves(tn_plan_s* p) {
+  const PlanCore& P = p->core;
+  std::vector<float2> host((size_t)P.leaves_elems, make_float2(0.f, 0.f));
+  for (const DevLeaf& d : P.dev_leaves)
+    for (size_t i = 0; i < d.data.size(); ++i)
+      host[d.stored_off + i] = make_float2((float)d.data[i].real(), (float)d.data[i].imag());
+  if (!host.empty())
+    HIP_TRY(hipMemcpy(p->d_leaves, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice),
+            "upload leaves");
+  return TN_OK;
+}
+
+// Enqueues one slice: bind, the per-step kernels, FP64 accumulation.
+static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
+  const PlanCore& P = p->core;
+  if (!P.binds.empty())
+    HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
+            "bind kernel");
+  for (const Op& op : P.ops) {
+    const float2* a = resolve(p, op.a);
+    const float2* b = resolve(p, op.b);
+    float2* c = const_cast<float2*>(resolve(p, op.c));
+    switch (op.kind) {
+      case kOpPermute:
+        HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
+        break;
+      case kOpGemm:
+        HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s), "gemm kernel");
+        break;
+      default:
+        HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
+        break;
+    }
+  }
+  HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
+  return TN_OK;
+}
+
+static void release(tn_plan_s* p) {
+  if (!p) return;
+  if (p->core.opts.dry_run) return;
+  hipSetDevice(p->device);
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  hipFree(p->d_leaves);
+  hipFree(p->d_bound);
+  hipFree(p->d_arena);
+  hipFree(p->d_binds);
+  hipFree(p->d_ctrl);
+}
+
+extern "C" {
+
+void tn_plan_opts_default(tn_plan_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->dtype = TN_DTYPE_C64;
+  o->gemm_form = TN_GEMM_AUTO;
+  o->max_log2 = 0;
+  o->use_graph = 1;
+  o->dry_run = 0;
+  o->device = 0;
+  o->host_fold_log2 = 12;
+  o->arena_bytes = 0;
+}
+
+const char* tn_last_error(void) { return g_err.c_str(); }
+
+int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, const int32_t* sliced_wires,
+            int32_t k, const int32_t* open_qubits, int32_t n_open, const tn_plan_opts* opts, tn_plan_t* out) {
+  if (!out) return fail(TN_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!c) return fail(TN_E_ARG, "circuit is NULL");
+  if (c->n_qubits < 1 || c->n_qubits > 4096) return fail(TN_E_ARG, "n_qubits out of range");
+  if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) return fail(TN_E_ARG, "bad gate list");
+  if (n_steps < 0 || (n_steps > 0 && !order_pairs)) return fail(TN_E_ARG, "bad order");
+  if (k < 0 || k > 62 || (k > 0 && !sliced_wires)) return fail(TN_E_ARG, "bad sliced-wire list");
+  if (n_open < 0 || n_open > 40 || (n_open > 0 && !open_qubits)) return fail(TN_E_ARG, "bad open-qubit list");
+  tn_plan_opts o;
+  if (opts)
+    o = *opts;
+  else
+    tn_plan_opts_default(&o);
+  if (o.dtype != TN_DTYPE_C64) return fail(TN_E_UNSUPPORTED, "only complex64 storage is built in this version");
+  if (o.host_fold_log2 < 0 || o.host_fold_log2 > 20) return fail(TN_E_ARG, "host_fold_log2 out of range");
+  for (int g = 0; g < c->n_gates; ++g) {
+    const tn_gate& G = c->gates[g];
+    if (G.nq != 1 && G.nq != 2) return fail(TN_E_ARG, "gate " + std::to_string(g) + ": nq must be 1 or 2");
+    for (int j = 0; j < G.nq; ++j)
+      if (G.q[j] < 0 || G.q[j] >= c->n_qubits)
+        return fail(TN_E_ARG, "gate " + std::to_string(g) + ": qubit out of range");
+    if (G.nq == 2 && G.q[0] == G.q[1]) return fail(TN_E_ARG, "gate " + std::to_string(g) + ": repeated qubit");
+  }
+  std::vector<bool> seen(c->n_qubits, false);
+  for (int i = 0; i < n_open; ++i) {
+    int q = open_qubits[i];
+    if (q < 0 || q >= c->n_qubits) return fail(TN_E_ARG, "open qubit out of range");
+    if (seen[q]) return fail(TN_E_ARG, "open qubit listed twice");
+    seen[q] = true;
+  }
+  if (n_open < c->n_qubits && !c->out_bits) return fail(TN_E_ARG, "out_bits is NULL but some qubits are closed");
+
+  tn_plan_s* p = new (std::nothrow) tn_plan_s();
+  if (!p) return fail(TN_E_MEM, "host allocation failed");
+  PlanCore& P = p->core;
+  P.n_qubits = c->n_qubits;
+  P.gates.assign(c->gates, c->gates + c->n_gates);
+  if (c->out_bits) P.out_bits.assign(c->out_bits, c->out_bits + c->n_qubits);
+  P.pairs.assign(order_pairs, order_pairs + 2 * n_steps);
+  P.sliced.assign(sliced_wires, sliced_wires + k);
+  P.open_q.assign(open_qubits, open_qubits + n_open);
+  P.opts = o;
+  std::string err;
+  int rc = build_plan(P, err);
+  if (rc) {
+    delete p;
+    return fail(rc, err);
+  }
+  p->device = o.device;
+  if (o.dry_run) {
+    *out = p;
+    return TN_OK;
+  }
+  // device side
+  auto bail = [&](int code) {
+    release(p);
+    delete p;
+    return code;
+  };
+  hipError_t e = hipSetDevice(o.device);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipMemGetInfo"));
+  const int64_t need = (P.arena_elems + P.leaves_elems + P.bound_elems) * (int64_t)sizeof(float2);
+  const int64_t budget = o.arena_bytes > 0 ? o.arena_bytes : (int64_t)(0.92 * (double)free_b);
+  if (need > budget)
+    return bail(fail(TN_E_MEM, "plan needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget)));
+  auto dmalloc = [&](void** ptr, int64_t bytes, const char* what) -> int {
+    if (bytes <= 0) bytes = 256;
+    hipError_t e2 = hipMalloc(ptr, (size_t)bytes);
+    if (e2 != hipSuccess) return hip_fail(e2, what);
+    return TN_OK;
+  };
+  if ((rc = dmalloc((void**)&p->d_leaves, P.leaves_elems * 8, "alloc leaves")) ||
+      (rc = dmalloc((void**)&p->d_bound, P.bound_elems * 8, "alloc bound leaves")) ||
+      (rc = dmalloc((void**)&p->d_arena, P.arena_elems * 8, "alloc arena")) ||
+      (rc = dmalloc((void**)&p->d_binds, (int64_t)P.binds.size() * (int64_t)sizeof(BindDesc), "alloc binds")) ||
+      (rc = dmalloc((void**)&p->d_ctrl, sizeof(Ctrl), "alloc control")))
+    return bail(rc);
+  if ((rc = upload_leaves(p))) return bail(rc);
+  if (!P.binds.empty()) {
+    e = hipMemcpy(p->d_binds, P.binds.data(), P.binds.size() * sizeof(BindDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload binds"));
+    for (auto& b : P.binds) p->bind_max = std::max(p->bind_max, b.n_elems);
+  }
+  Ctrl zero{};
+  e = hipMemcpy(p->d_ctrl, &zero, sizeof(Ctrl), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(e, "init control"));
+  *out = p;
+  return TN_OK;
+}
+
+int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream) {
+  if (!p) return fail(TN_E_ARG, "plan is NULL");
+  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
+  if (!amp) return fail(TN_E_ARG, "amp is NULL");
+  const int64_t ns = p->core.stats.n_slices;
+  if (s_begin < 0 || s_end < s_begin || s_end > ns)
+    return fail(TN_E_ARG, "slice range [" + std::to_string(s_begin) + ", " + std::to_string(s_end) +
+                              ") outside [0, " + std::to_string(ns) + ")");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  p->last_stream = s;
+  p->ran = true;
+  if (s_end == s_begin) return TN_OK;
+  HIP_TRY(launch_set_ctrl(p->d_ctrl, s_begin, amp, s), "control kernel");
+  if (p->core.opts.use_graph) {
+    if (!p->exec) {
+      if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "create capture stream");
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      int rc = enqueue_slice(p, p->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "end capture");
+      p->graph = g;
+      HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate graph");
+    }
+    for (int64_t sl = s_begin; sl < s_end; ++sl) HIP_TRY(hipGraphLaunch(p->exec, s), "graph launch");
+  } else {
+    for (int64_t sl = s_begin; sl < s_end; ++sl) {
+      int rc = enqueue_slice(p, s);
+      if (rc) return rc;
+    }
+  }
+  return TN_OK;
+}
+
+int tn_plan_profile(tn_plan_t p, int64_t slice, void* amp, void* stream, float* op_ms, int32_t cap,
+                    int32_t* n_ops) {
+  if (!p || !amp || !n_ops) return fail(TN_E_ARG, "NULL argument");
+  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
+  const PlanCore& P = p->core;
+  const int nk = (int)P.ops.size() + 1;
+  *n_ops = nk;
+  if (!op_ms || cap < nk) return fail(TN_E_ARG, "op_ms capacity below the kernel count");
+  if (slice < 0 || slice >= P.stats.n_slices) return fail(TN_E_ARG, "slice out of range");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  p->last_stream = s;
+  p->ran = true;
+  std::vector<hipEvent_t> ev(nk + 1, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e), "event create");
+  int rc = TN_OK;
+  auto body = [&]() -> int {
+    HIP_TRY(launch_set_ctrl(p->d_ctrl, slice, amp, s), "control kernel");
+    if (!P.binds.empty())
+      HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
+              "bind kernel");
+    for (int i = 0; i < (int)P.ops.size(); ++i) {
+      const Op& op = P.ops[i];
+      const float2* a = resolve(p, op.a);
+      const float2* b = resolve(p, op.b);
+      float2* c = const_cast<float2*>(resolve(p, op.c));
+      HIP_TRY(hipEventRecord(ev[i], s), "event record");
+      switch (op.kind) {
+        case kOpPermute:
+          HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
+          break;
+        case kOpGemm:
+          HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s), "gemm kernel");
+          break;
+        default:
+          HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
+          break;
+      }
+    }
+    HIP_TRY(hipEventRecord(ev[nk - 1], s), "event record");
+    HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
+    HIP_TRY(hipEventRecord(ev[nk], s), "event record");
+    HIP_TRY(hipEventSynchronize(ev[nk]), "event synchronize");
+    for (int i = 0; i < nk; ++i) HIP_TRY(hipEventElapsedTime(&op_ms[i], ev[i], ev[i + 1]), "event elapsed");
+    return TN_OK;
+  };
+  rc = body();
+  for (auto& e : ev)
+    if (e) hipEventDestroy(e);
+  return rc;
+}
+
+int tn_plan_info(tn_plan_t p, tn_plan_stats* s) {
+  if (!p || !s) return fail(TN_E_ARG, "NULL argument");
+  *s = p->core.stats;
+  return TN_OK;
+}
+
+int tn_plan_json(tn_plan_t p, char* buf, int64_t cap, int64_t* needed) {
+  if (!p) return fail(TN_E_ARG, "plan is NULL");
+  const std::string& j = p->core.json;
+  if (needed) *needed = (int64_t)j.size() + 1;
+  if (buf) {
+    if (cap < (int64_t)j.size() + 1) return fail(TN_E_ARG, "buffer too small");
+    std::memcpy(buf, j.c_str(), j.size() + 1);
+  }
+  return TN_OK;
+}
+
+int tn_plan_leaf(tn_plan_t p, int32_t i, double* out, int64_t cap) {
+  if (!p || !out) return fail(TN_E_ARG, "NULL argument");
+  if (i < 0 || i >= (int32_t)p->core.dev_leaves.size()) return fail(TN_E_ARG, "leaf index out of range");
+  const DevLeaf& d = p->core.dev_leaves[i];
+  if (cap < 2 * (int64_t)d.data.size()) return fail(TN_E_ARG, "buffer too small");
+  for (size_t j = 0; j < d.data.size(); ++j) {
+    out[2 * j] = d.data[j].real();
+    out[2 * j + 1] = d.data[j].imag();
+  }
+  return TN_OK;
+}
+
+int tn_plan_status(tn_plan_t p, uint32_t* flags) {
+  if (!p || !flags) return fail(TN_E_ARG, "NULL argument");
+  *flags = 0;
+  if (p->core.opts.dry_run || !p->ran) return TN_OK;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(p->last_stream), "stream synchronize");
+  Ctrl c{};
+  HIP_TRY(hipMemcpy(&c, p->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost), "read control");
+  *flags = c.flags;
+  return TN_OK;
+}
+
+int tn_plan_set_output_bits(tn_plan_t p, const uint8_t* out_bits) {
+  if (!p || !out_bits) return fail(TN_E_ARG, "NULL argument");
+  PlanCore& P = p->core;
+  P.out_bits.assign(out_bits, out_bits + P.n_qubits);
+  std::string err;
+  int rc = refold_leaves(P, err);
+  if (rc) return fail(rc, err);
+  if (P.opts.dry_run) return TN_OK;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  if (p->ran) HIP_TRY(hipStreamSynchronize(p->last_stream), "stream synchronize");
+  return upload_leaves(p);
+}
+
+int tn_plan_destroy(tn_plan_t p) {
+  if (!p) return TN_OK;
+  if (!p->core.opts.dry_run && p->ran) {
+    hipSetDevice(p->device);
+    hipStreamSynchronize(p->last_stream);
+  }
+  release(p);
+  delete p;
+  return TN_OK;
+}
+
+int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm, int64_t batch, void* stream) {
+  if (!in || !out || !perm) return fail(TN_E_ARG, "NULL argument");
+  if (rank < 0 || rank > 40 || batch < 0) return fail(TN_E_ARG, "rank or batch out of range");
+  hipError_t e = launch_permute_c64((const float2*)in, (float2*)out, rank, perm, batch, (hipStream_t)stream);
+  if (e == hipErrorInvalidValue) return fail(TN_E_ARG, "perm is not a permutation of 0..rank-1");
+  if (e != hipSuccess) return hip_fail(e, "permute kernel");
+  return TN_OK;
+}
+
+int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K, int64_t batch,
+                 int32_t form, void* stream) {
+  if (!A || !B || !C) return fail(TN_E_ARG, "NULL argument");
+  if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
+  if (!gemm_shape_ok(M, N, K) || batch < 0)
+    return fail(TN_E_ARG, "shape not supported: M, N multiples of 64, K a multiple of 16");
+  hipError_t e = launch_gemm_c64((const float2*)A, (const float2*)B, (float2*)C, M, N, K, batch, form,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gemm kernel");
+  return TN_OK;
+}
+
+int tn_amp_norm2(const void* amp, int64_t n, void* out_dev, void* stream) {
+  if (!amp || !out_dev || n < 0) return fail(TN_E_ARG, "bad argument");
+  hipError_t e = launch_norm2((const double*)amp, n, (double*)out_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "norm kernel");
+  return TN_OK;
+}
+
+int tn_amp_xeb(const void* amp, int64_t n, const void* idx_dev, int64_t n_idx, void* out_dev, void* stream) {
+  if (!amp || !out_dev || (n_idx > 0 && !idx_dev) || n < 0 || n_idx < 0) return fail(TN_E_ARG, "bad argument");
+  hipError_t e = launch_xeb((const double*)amp, n, (const int64_t*)idx_dev, n_idx, (double*)out_dev,
+                            (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "xeb kernel");
+  return TN_OK;
+}
+
+int tn_amp_hist(const void* amp, int64_t n, double scale, double xmax, int32_t n_bins, void* counts_dev,
+                void* stream) {
+  if (!amp || !counts_dev || n < 0 || n_bins < 1 || !(xmax > 0)) return fail(TN_E_ARG, "bad argument");
+  hipError_t e = launch_hist((const double*)amp, n, scale, xmax, n_bins, (unsigned long long*)counts_dev,
+                             (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "histogram kernel");
+  return TN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal data structures shared by the planner (host C++) and the HIP
+// runtime of the tnrcs library.  Not part of the C ABI.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tnrcs.h"
+
+namespace tnrcs {
+
+constexpr int kMaxRank = 48;  // bits of a device tensor index
+constexpr int kMaxRuns = 48;  // runs of a bit-deposit map
+
+// Bit-deposit map: value bit (src + i) goes to target bit (dst + i) for
+// i < len, for each run.  Built from "value bit j -> target position pos[j]".
+struct Runs {
+  int32_t n = 0;
+  int8_t src[kMaxRuns] = {};
+  int8_t dst[kMaxRuns] = {};
+  int8_t len[kMaxRuns] = {};
+};
+
+bool make_runs(const std::vector<int>& pos, Runs* r);  // false if too many runs
+
+enum Region : int32_t { kArena = 0, kLeaves = 1, kBound = 2 };
+
+struct TRef {
+  int32_t region = kArena;
+  int64_t off = 0;  // element offset (complex elements) within the region
+};
+
+enum OpKind : int32_t { kOpPermute = 0, kOpGemm = 1, kOpGeneric = 2, kOpSkinny = 3 };
+
+// Permute: output position q takes input position perm[q].
+struct PermuteOp {
+  int32_t rank = 0;
+  int32_t perm[kMaxRank] = {};
+};
+
+// GEMM: C[M][N] = sum_k A[M][K] * B[N][K]   (row-major, complex)
+struct GemmOp {
+  int64_t M = 0, N = 0, K = 0;
+  int32_t form = TN_GEMM_4M;
+  int32_t split_k = 1;  // K split into this many partial products (summed in a second pass)
+};
+
+// Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],
+// C index = (m << nN) | n.
+struct IndexOp {
+  int32_t nM = 0, nN = 0, nK = 0;
+  Runs aM, aK, bN, bK;
+  // skinny tiling (planner-chosen): the tile holds the low tM M-bits and the
+  // low tK K-bits of the chunk; the remaining bits index tiles / chunks.
+  int32_t tM = 0, tK = 0;
+};
+
+struct Op {
+  int32_t kind = kOpGeneric;
+  int32_t step = -1;  // SSA step this op belongs to
+  TRef a, b, c;       // permute: a = in, c = out
+  PermuteOp perm;
+  GemmOp gemm;
+  IndexOp idx;
+  double flops = 0;   // algorithmic (8 per complex MAC)
+  double bytes = 0;   // bytes moved by this kernel
+};
+
+// A device leaf: stored once for all slices with its sliced wires as the top
+// bits; per slice the bind kernel copies the selected sub-tensor to `bound`.
+struct DevLeaf {
+  int32_t ssa = -1;
+  std::vector<int> layout;   // stored layout, most significant first (sliced wires first)
+  int32_t n_sliced = 0;      // leading entries of layout that are sliced wires
+  std::vector<int> slice_bit;  // per leading sliced wire: its index j in the sliced list
+  int64_t stored_off = 0;    // element offset in the leaves region
+  int64_t bound_off = 0;     // element offset in the bound region (if n_sliced > 0)
+  std::vector<std::complex<double>> data;  // FP64 values in the stored layout
+};
+
+struct BindDesc {  // device-side descriptor of one sliced leaf
+  int64_t src_off, dst_off, n_elems;
+  int32_t n_sl;
+  int32_t sbit[8];
+  int32_t pos[8];
+};
+
+struct AccumDesc {
+  int32_t n_open = 0;
+  Runs y2root;  // amplitude index bits -> root layout positions
+  TRef root;
+};
+
+struct HostTensor {
+  std::vector<int> wires;  // most significant first
+  std::vector<std::complex<double>> data;
+};
+
+struct PlanCore {
+  // inputs (copied)
+  int32_t n_qubits = 0;
+  std::vector<tn_gate> gates;
+  std::vector<uint8_t> out_bits;
+  std::vector<int32_t> pairs;
+  std::vector<int32_t> sliced;
+  std::vector<int32_t> open_q;
+  tn_plan_opts opts{};
+
+  // network
+  int32_t n_leaves = 0, n_wires = 0;
+  std::vector<std::vector<int>> leaf_wires;
+  std::vector<int> open_wires;
+  std::vector<int> wire_slice_idx;  // wire -> j or -1
+
+  // host part
+  std::vector<bool> on_host;   // per SSA id
+  int32_t n_host_steps = 0;
+  std::vector<DevLeaf> dev_leaves;
+  std::vector<BindDesc> binds;
+  int64_t leaves_elems = 0, bound_elems = 0;
+
+  // device part
+  std::vector<Op> ops;
+  AccumDesc accum;
+  int64_t arena_elems = 0;
+  int32_t root_is_leaf = 0;
+  tn_plan_stats stats{};
+  std::string json;
+};
+
+// Planner entry (host only).  Returns TN_OK or an error code with a message.
+int build_plan(PlanCore& P, std::string& err);
+// Re-folds the leaves after an output-bit change (same structure).
+int refold_leaves(PlanCore& P, std::string& err);
+
+}  // namespace tnrcs

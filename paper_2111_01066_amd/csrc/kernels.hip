@@ -1,0 +1,433 @@
+// gfx950 kernels of the tnrcs library: slice binding, tiled binary-index
+// permutation, complex GEMM from real MFMA products (4M / 3M), generic
+// gathered contraction, FP64 slice accumulation and FP64 reductions.
+//
+// Paper anchors: each pairwise contraction is an index permutation followed by
+// a complex matrix product (Supplement Eq. (matmul)); slicing sums smaller
+// networks (main text, customized-TNC section); XEB / Porter-Thomas checks
+// (main text Eq. (fxeb)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "kernels.h"
+
+namespace tnrcs {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
+  uint64_t o = 0;
+  for (int i = 0; i < r.n; ++i) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
+  return o;
+}
+
+// ---------------------------------------------------------------- control --
+
+__global__ void k_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp) {
+  ctrl->cursor = cursor;
+  ctrl->amp = (double*)amp;
+}
+
+hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(1), 0, s, ctrl, cursor, amp);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- bind --
+// Copies, for every sliced leaf, the sub-tensor selected by the current slice
+// id (its sliced wires are the leaf's top bits) into the bound-leaf region.
+
+__global__ __launch_bounds__(256) void k_bind(const float2* __restrict__ leaves, float2* __restrict__ bound,
+                                              const BindDesc* __restrict__ descs, const Ctrl* __restrict__ ctrl) {
+  const BindDesc& d = descs[blockIdx.y];
+  const int64_t s = ctrl->cursor;
+  int64_t off = 0;
+  for (int i = 0; i < d.n_sl; ++i) off |= ((s >> d.sbit[i]) & 1ll) << d.pos[i];
+  const float2* src = leaves + d.src_off + off;
+  float2* dst = bound + d.dst_off;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.n_elems;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+hipError_t launch_bind(const float2* leaves, float2* bound, const BindDesc* descs, int n_desc, int64_t max_elems,
+                       const Ctrl* ctrl, hipStream_t s) {
+  if (n_desc <= 0) return hipSuccess;
+  int64_t gx = std::min<int64_t>((max_elems + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_bind, dim3((unsigned)std::max<int64_t>(gx, 1), n_desc), dim3(256), 0, s, leaves, bound,
+                     descs, ctrl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- permute --
+// Tile = the input-fast bits I plus the output-fast bits O of the index.  A
+// tile is read with runs of 2^|I| consecutive input elements, staged in LDS,
+// and written with runs of 2^|O| consecutive output elements.
+
+constexpr int kPermTileBits = 12;
+constexpr int kPermThreads = 256;
+
+struct PermArgs {
+  int64_t n_tiles;
+  int64_t stride;  // batch stride (elements)
+  int32_t tbits;
+  Runs in_tile;   // tile element e (input-ascending T order) -> input offset
+  Runs out_tile;  // tile element f (output-ascending T order) -> output offset
+  Runs f2e;       // f -> e
+  Runs id_in;     // tile id -> input offset
+  Runs id_out;    // tile id -> output offset
+};
+
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+
+__global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restrict__ in, float2* __restrict__ out,
+                                                         const PermArgs a) {
+  __shared__ float2 tile[(1 << kPermTileBits) + (1 << (kPermTileBits - 4))];
+  const int tid = threadIdx.x;
+  const int nt = 1 << a.tbits;
+  const float2* src = in + (int64_t)blockIdx.y * a.stride;
+  float2* dst = out + (int64_t)blockIdx.y * a.stride;
+  const uint64_t e_t = dep((uint64_t)tid, a.in_tile);
+  const uint64_t f_t = dep((uint64_t)tid, a.out_tile);
+  const uint64_t fe_t = dep((uint64_t)tid, a.f2e);
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    const uint64_t ib = dep((uint64_t)t, a.id_in);
+    const uint64_t ob = dep((uint64_t)t, a.id_out);
+    for (int i = 0; i < nt; i += kPermThreads) {
+      const int e = i + tid;
+      if (e < nt) {
+        const uint64_t off = ib | e_t | dep((uint64_t)i, a.in_tile);
+        tile[lds_pad(e)] = src[off];
+      }
+    }
+    __syncthreads();
+    for (int i = 0; i < nt; i += kPermThreads) {
+      const int f = i + tid;
+      if (f < nt) {
+        const uint64_t off = ob | f_t | dep((uint64_t)i, a.out_tile);
+        const int e = (int)(fe_t | dep((uint64_t)i, a.f2e));
+        dst[off] = tile[lds_pad(e)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int32_t* perm, int64_t batch,
+                              hipStream_t s) {
+  // inverse map: input position p -> output position inv[p]
+  std::vector<int> inv(rank, -1);
+  for (int q = 0; q < rank; ++q) {
+    if (perm[q] < 0 || perm[q] >= rank || inv[perm[q]] >= 0) return hipErrorInvalidValue;
+    inv[perm[q]] = q;
+  }
+  // choose the tile: grow input-fast and output-fast bit sets alternately
+  std::vector<bool> inT(rank, false);
+  int tb = 0, a = 0, b = 0;
+  const int cap = std::min(kPermTileBits, rank);
+  while (tb < cap) {
+    bool grew = false;
+    if (a < rank && (a <= b || b >= rank)) {
+      if (!inT[a]) {
+        inT[a] = true;
+        ++tb;
+      }
+      ++a;
+      grew = true;
+    } else if (b < rank) {
+      int p = perm[b];
+      if (!inT[p]) {
+        inT[p] = true;
+        ++tb;
+      }
+      ++b;
+      grew = true;
+    }
+    if (!grew) break;
+  }
+  std::vector<int> Tin, Tout, R;
+  for (int p = 0; p < rank; ++p) (inT[p] ? Tin : R).push_back(p);
+  Tout = Tin;
+  std::sort(Tout.begin(), Tout.end(), [&](int x, int y) { return inv[x] < inv[y]; });
+  PermArgs A{};
+  A.tbits = (int)Tin.size();
+  A.n_tiles = (int64_t)1 << (rank - A.tbits);
+  A.stride = (int64_t)1 << rank;
+  std::vector<int> p1, p2, p3, p4, p5;
+  for (int p : Tin) p1.push_back(p);
+  for (int p : Tout) p2.push_back(inv[p]);
+  for (int p : Tout) p3.push_back((int)(std::find(Tin.begin(), Tin.end(), p) - Tin.begin()));
+  for (int p : R) p4.push_back(p);
+  for (int p : R) p5.push_back(inv[p]);
+  if (!make_runs(p1, &A.in_tile) || !make_runs(p2, &A.out_tile) || !make_runs(p3, &A.f2e) ||
+      !make_runs(p4, &A.id_in) || !make_runs(p5, &A.id_out))
+    return hipErrorInvalidValue;
+  int64_t grid = std::min<int64_t>(A.n_tiles, 8192);
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)grid, (unsigned)batch), dim3(kPermThreads), 0, s, in, out, A);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- GEMM --
+// C[M][N] = sum_k A[M][K] B[N][K], complex64 in and out, FP32 accumulation on
+// v_mfma_f32_32x32x2_f32.  4M form: Cr += ArBr + (-Ai)Bi, Ci += ArBi + AiBr
+// (four real products).  3M form: T1 = ArBr, T2 = AiBi,
+// T3 = (Ar+Ai)(Br+Bi); Cr = T1 - T2, Ci = T3 - T1 - T2 (three products).
+// Workgroup tile 64x64, four waves of 32x32, K staged through LDS in steps of
+// 16 with re/im split into planar arrays.
+
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, const float2* __restrict__ B,
+                                              float2* __restrict__ C, int64_t M, int64_t N, int64_t K) {
+  __shared__ float As[2][GBK][GBM + 4];
+  __shared__ float Bs[2][GBK][GBN + 4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t bm = (int64_t)blockIdx.x * GBM, bn = (int64_t)blockIdx.y * GBN;
+  const int64_t z = blockIdx.z;
+  A += z * M * K;
+  B += z * N * K;
+  C += z * M * N;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  floatx16 c0 = {}, c1 = {}, c2 = {};
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+  const float2* Ap = A + (bm + lrow) * K + lk;
+  const float2* Bp = B + (bn + lrow) * K + lk;
+  for (int64_t k0 = 0; k0 < K; k0 += GBK) {
+    const float4 a01 = *reinterpret_cast<const float4*>(Ap + k0);
+    const float4 a23 = *reinterpret_cast<const float4*>(Ap + k0 + 2);
+    const float4 b01 = *reinterpret_cast<const float4*>(Bp + k0);
+    const float4 b23 = *reinterpret_cast<const float4*>(Bp + k0 + 2);
+    As[0][lk + 0][lrow] = a01.x;
+    As[1][lk + 0][lrow] = a01.y;
+    As[0][lk + 1][lrow] = a01.z;
+    As[1][lk + 1][lrow] = a01.w;
+    As[0][lk + 2][lrow] = a23.x;
+    As[1][lk + 2][lrow] = a23.y;
+    As[0][lk + 3][lrow] = a23.z;
+    As[1][lk + 3][lrow] = a23.w;
+    Bs[0][lk + 0][lrow] = b01.x;
+    Bs[1][lk + 0][lrow] = b01.y;
+    Bs[0][lk + 1][lrow] = b01.z;
+    Bs[1][lk + 1][lrow] = b01.w;
+    Bs[0][lk + 2][lrow] = b23.x;
+    Bs[1][lk + 2][lrow] = b23.y;
+    Bs[0][lk + 3][lrow] = b23.z;
+    Bs[1][lk + 3][lrow] = b23.w;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float ar = As[0][kr][wm + (lane & 31)];
+      const float ai = As[1][kr][wm + (lane & 31)];
+      const float br = Bs[0][kr][wn + (lane & 31)];
+      const float bi = Bs[1][kr][wn + (lane & 31)];
+      if (FORM == TN_GEMM_3M) {
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, c2, 0, 0, 0);
+      } else {
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c0, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, c1, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int j = lane & 31;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    float2 v;
+    if (FORM == TN_GEMM_3M) {
+      v.x = c0[r] - c1[r];
+      v.y = c2[r] - c0[r] - c1[r];
+    } else {
+      v.x = c0[r];
+      v.y = c1[r];
+    }
+    C[(bm + wm + i) * N + bn + wn + j] = v;
+  }
+}
+
+bool gemm_shape_ok(int64_t M, int64_t N, int64_t K) {
+  return M > 0 && N > 0 && K > 0 && M % GBM == 0 && N % GBN == 0 && K % GBK == 0;
+}
+
+hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
+                           int64_t batch, int form, hipStream_t s) {
+  if (!gemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
+  if (batch == 0) return hipSuccess;
+  dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)batch);
+  if (form == TN_GEMM_3M)
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+  else
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- generic --
+// One output element per thread: C[(m<<nN)|n] = sum_k A[dep(m)|dep(k)] B[dep(n)|dep(k)].
+
+__global__ __launch_bounds__(256) void k_generic(const float2* __restrict__ A, const float2* __restrict__ B,
+                                                float2* __restrict__ C, const IndexOp op) {
+  const int64_t nC = (int64_t)1 << (op.nM + op.nN);
+  const int64_t nK = (int64_t)1 << op.nK;
+  const uint64_t nmask = (1ull << op.nN) - 1ull;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nC; c += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = (uint64_t)c >> op.nN, n = (uint64_t)c & nmask;
+    const uint64_t ab = dep(m, op.aM), bb = dep(n, op.bN);
+    float re = 0.f, im = 0.f;
+    for (int64_t k = 0; k < nK; ++k) {
+      const float2 x = A[ab | dep((uint64_t)k, op.aK)];
+      const float2 y = B[bb | dep((uint64_t)k, op.bK)];
+      re = fmaf(x.x, y.x, re);
+      re = fmaf(-x.y, y.y, re);
+      im = fmaf(x.x, y.y, im);
+      im = fmaf(x.y, y.x, im);
+    }
+    C[c] = make_float2(re, im);
+  }
+}
+
+hipError_t launch_generic_c64(const float2* A, const float2* B, float2* C, const IndexOp& op, hipStream_t s) {
+  const int64_t nC = (int64_t)1 << (op.nM + op.nN);
+  int64_t grid = std::min<int64_t>((nC + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_generic, dim3((unsigned)grid), dim3(256), 0, s, A, B, C, op);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ accumulate --
+// amp[y] += (double) root[dep(y)] for the current slice; raises the
+// non-finite flag; advances the slice cursor.
+
+__global__ __launch_bounds__(256) void k_accum(const float2* __restrict__ root, const Runs y2root, int n_open,
+                                              Ctrl* ctrl) {
+  double* amp = ctrl->amp;
+  const int64_t n = (int64_t)1 << n_open;
+  bool bad = false;
+  for (int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; y < n; y += (int64_t)gridDim.x * blockDim.x) {
+    const float2 v = root[dep((uint64_t)y, y2root)];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+    amp[2 * y] += (double)v.x;
+    amp[2 * y + 1] += (double)v.y;
+  }
+  if (bad) atomicOr(&ctrl->flags, (unsigned)TN_FLAG_NONFINITE);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->cursor += 1;
+}
+
+hipError_t launch_accum(const float2* root, const AccumDesc& d, Ctrl* ctrl, hipStream_t s) {
+  const int64_t n = (int64_t)1 << d.n_open;
+  int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_accum, dim3((unsigned)grid), dim3(256), 0, s, root, d.y2root, d.n_open, ctrl);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- reductions --
+// Deterministic two-pass FP64 sums: fixed grid of per-block partials, then
+// one block sums the partials in a fixed order.
+
+constexpr int kRedBlocks = 1024;
+
+__device__ double block_sum(double v) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_norm2_part(const double* __restrict__ amp, int64_t n, double* part) {
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double re = amp[2 * i], im = amp[2 * i + 1];
+    s += re * re + im * im;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_xeb_part(const double* __restrict__ amp, int64_t n,
+                                                 const int64_t* __restrict__ idx, int64_t n_idx, double* part) {
+  double s1 = 0, s2 = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_idx;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = idx[i];
+    if (j < 0 || j >= n) continue;
+    const double re = amp[2 * j], im = amp[2 * j + 1];
+    const double p = re * re + im * im;
+    s1 += p;
+    s2 += p * p;
+  }
+  s1 = block_sum(s1);
+  s2 = block_sum(s2);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_final_sum(const double* __restrict__ part, int nblk, int width,
+                                                  double* out) {
+  for (int w = 0; w < width; ++w) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[i * width + w];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[w] = s;
+  }
+}
+
+hipError_t launch_norm2(const double* amp, int64_t n, double* out, hipStream_t s) {
+  double* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, kRedBlocks * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norm2_part, dim3(kRedBlocks), dim3(256), 0, s, amp, n, part);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, part, kRedBlocks, 1, out);
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(part, s);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_xeb(const double* amp, int64_t n, const int64_t* idx, int64_t n_idx, double* out, hipStream_t s) {
+  double* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, 2 * kRedBlocks * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_xeb_part, dim3(kRedBlocks), dim3(256), 0, s, amp, n, idx, n_idx, part);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, part, kRedBlocks, 2, out);
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(part, s);
+  return e != hipSuccess ? e : e2;
+}
+
+__global__ __launch_bounds__(256) void k_hist(const double* __restrict__ amp, int64_t n, double scale, double xmax,
+                                             int n_bins, unsigned long long* counts) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double re = amp[2 * i], im = amp[2 * i + 1];
+    const double x = scale * (re * re + im * im);
+    int b = x >= xmax ? n_bins - 1 : (int)(x / xmax * n_bins);
+    if (b < 0) b = 0;
+    if (b >= n_bins) b = n_bins - 1;
+    atomicAdd(&counts[b], 1ull);
+  }
+}
+
+hipError_t launch_hist(const double* amp, int64_t n, double scale, double xmax, int n_bins,
+                       unsigned long long* counts, hipStream_t s) {
+  int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist, dim3((unsigned)grid), dim3(256), 0, s, amp, n, scale, xmax, n_bins, counts);
+  return hipGetLastError();
+}
+
+}  // namespace tnrcs

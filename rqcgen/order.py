@@ -236,7 +236,7 @@ def live_peak(ns: NetworkStructure, pairs, sliced: Sequence[int] = ()) -> float:
 
 def slice_to_fit(ns: NetworkStructure, pairs, max_log2: int,
                  max_live_elems: Optional[float] = None,
-                 exclude: Sequence[int] = ()) -> List[int]:
+                 exclude: Sequence[int] = (), initial: Sequence[int] = ()) -> List[int]:
     """Greedy index slicing: repeatedly slice the wire that minimizes the total
     flop count (per-slice cost x number of slices) among the wires of the
     largest intermediates, until every tensor of one slice has at most
@@ -260,8 +260,11 @@ def slice_to_fit(ns: NetworkStructure, pairs, max_log2: int,
             C[i, widx[w]] = True
         urank[i] = _popcount(ma | mb)
         crank[i] = _popcount(mc)
-    sliced: List[int] = []
+    sliced: List[int] = list(initial)
     sl = np.zeros(len(wires), dtype=bool)
+    for w in initial:
+        if w in widx:
+            sl[widx[w]] = True
     while True:
         ur = urank - U[:, sl].sum(axis=1)
         cr = crank - C[:, sl].sum(axis=1)

@@ -1,0 +1,97 @@
+"""GPU kernels through the C ABI: permute (bit-exact vs numpy), complex GEMM
+4M/3M (vs FP64 numpy), FP64 reductions."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2111_01066_amd import tnrcs  # noqa: E402
+
+DEV = "cuda"
+
+
+def _np_permute(x, perm):
+    r = len(perm)
+    o = np.arange(1 << r, dtype=np.int64)
+    i = np.zeros_like(o)
+    for q, p in enumerate(perm):
+        i |= ((o >> q) & 1) << p
+    return x[..., i]
+
+
+def _rand_c64(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+@pytest.mark.parametrize("rank", [0, 1, 2, 3, 5, 8, 11, 12, 13, 16, 20, 23])
+def test_permute_bit_exact(rank):
+    rng = np.random.default_rng(rank)
+    for trial in range(3):
+        perm = rng.permutation(rank).tolist()
+        if trial == 1:
+            perm = list(range(rank))
+        if trial == 2 and rank > 4:
+            perm = list(range(rank))[::-1]
+        x = _rand_c64(rng, 2, 1 << rank)
+        xin = torch.from_numpy(x).to(DEV)
+        out = torch.empty_like(xin)
+        print(f"permute rank={rank} trial={trial}", flush=True)
+        tnrcs.tn_permute_c64(xin, out, perm, batch=2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
+
+
+def test_permute_rejects_bad_perm():
+    x = torch.zeros(8, dtype=torch.complex64, device=DEV)
+    with pytest.raises(tnrcs.TnError):
+        tnrcs.tn_permute_c64(x, torch.empty_like(x), [0, 0, 1])
+
+
+@pytest.mark.parametrize("form", ["4m", "3m"])
+@pytest.mark.parametrize("M,N,K,batch", [(64, 64, 16, 1), (128, 64, 48, 2), (256, 192, 512, 1),
+                                         (64, 512, 4096, 1)])
+def test_cgemm_matches_fp64(form, M, N, K, batch):
+    rng = np.random.default_rng(M + N + K)
+    A = _rand_c64(rng, batch, M, K)
+    B = _rand_c64(rng, batch, N, K)
+    ref = np.einsum("bmk,bnk->bmn", A.astype(np.complex128), B.astype(np.complex128))
+    dA, dB = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    dC = torch.empty((batch, M, N), dtype=torch.complex64, device=DEV)
+    print(f"cgemm {form} M={M} N={N} K={K} batch={batch}", flush=True)
+    tnrcs.tn_cgemm_c64(dA, dB, dC, M, N, K, batch, form)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().astype(np.complex128)
+    # FP32 accumulation over K terms: normwise error ~ sqrt(K) * 2^-24 relative
+    err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    assert err < 4e-7 * np.sqrt(K) + 1e-6, err
+
+
+def test_cgemm_rejects_bad_shape():
+    x = torch.zeros(64 * 64, dtype=torch.complex64, device=DEV)
+    with pytest.raises(tnrcs.TnError):
+        tnrcs.tn_cgemm_c64(x, x, x, 64, 64, 8, 1, "4m")
+
+
+def test_reductions():
+    rng = np.random.default_rng(3)
+    n = 1 << 18
+    a = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * 1e-3
+    d = torch.from_numpy(a).to(DEV)
+    out = torch.zeros(2, dtype=torch.float64, device=DEV)
+    tnrcs.tn_amp_norm2(d, n, out)
+    torch.cuda.synchronize()
+    assert abs(out[0].item() - np.sum(np.abs(a) ** 2)) < 1e-12 * np.sum(np.abs(a) ** 2)
+    idx = rng.integers(0, n, size=5000)
+    didx = torch.from_numpy(idx).to(DEV)
+    tnrcs.tn_amp_xeb(d, n, didx, idx.size, out)
+    torch.cuda.synchronize()
+    p = np.abs(a[idx]) ** 2
+    np.testing.assert_allclose(out.cpu().numpy(), [p.sum(), (p * p).sum()], rtol=1e-12)
+    counts = torch.zeros(16, dtype=torch.int64, device=DEV)
+    scale = n / np.sum(np.abs(a) ** 2)
+    tnrcs.tn_amp_hist(d, n, scale, 8.0, 16, counts)
+    torch.cuda.synchronize()
+    x = scale * np.abs(a) ** 2
+    ref = np.minimum((x / 8.0 * 16).astype(np.int64), 15)
+    np.testing.assert_array_equal(counts.cpu().numpy(), np.bincount(ref, minlength=16))

@@ -1,0 +1,129 @@
+"""The C++ planner on the CPU (dry-run plans, no device): its step list, run
+by a NumPy interpreter over stand-in device regions, reproduces the oracle.
+Also the C ABI's argument validation and exported symbols."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_01066_amd import tnrcs
+from rqcgen import (make_rqc, network_structure, greedy_order, slice_to_fit, random_bitstrings,
+                    Circuit, Gate)
+from rqcgen.order import bisection_order
+from tests.plan_interp import PlanInterpreter
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run_plan(plan, n_slices, n_open):
+    it = PlanInterpreter(plan)
+    amp = np.zeros(1 << n_open, dtype=np.complex128)
+    for s in range(n_slices):
+        it.run_slice(s, amp)
+    return amp
+
+
+CASES = [
+    # rows, cols, d, seed, open, finder, S, fold
+    (4, 5, 8, 0, list(range(20)), "bisection", 40, 12),
+    (4, 5, 8, 0, list(range(20)), "greedy", 40, 12),
+    (4, 5, 8, 0, [], "bisection", 40, 12),
+    (3, 4, 8, 1, [0, 5, 11], "bisection", 10, 12),
+    (3, 4, 8, 1, [0, 5, 11], "greedy", 8, 4),
+    (3, 4, 6, 2, [2, 3], "bisection", 9, 0),
+    (2, 3, 10, 3, list(range(6)), "greedy", 40, 20),
+]
+
+
+@pytest.mark.parametrize("rows,cols,d,seed,open_q,finder,S,fold", CASES)
+def test_dryrun_plan_matches_oracle(rows, cols, d, seed, open_q, finder, S, fold):
+    c = make_rqc(rows, cols, d, seed)
+    bits = random_bitstrings(c.n_qubits, 1, seed=seed + 100)[0]
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0) if finder == "bisection" else greedy_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, S)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True, host_fold_log2=fold)
+    info = plan.info()
+    assert info["n_slices"] == 1 << len(sliced)
+    assert info["n_host_steps"] + info["n_device_steps"] == len(pairs)
+    amp = _run_plan(plan, info["n_slices"], len(open_q))
+    ref = oracle.amplitudes_sv(c, open_q, bits)
+    np.testing.assert_allclose(amp, ref, atol=1e-12)
+    plan.close()
+
+
+@pytest.mark.parametrize("d,open_q,S", [(12, [], 22), (10, [0, 1, 2, 3, 4, 5], 20)])
+def test_dryrun_dense_steps_present(d, open_q, S):
+    c = make_rqc(4, 5, d, 5)
+    bits = random_bitstrings(20, 1, seed=8)[0]
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, S)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True)
+    info = plan.info()
+    assert info["n_dense"] > 0
+    amp = _run_plan(plan, info["n_slices"], len(open_q))
+    ref = oracle.amplitudes_sv(c, open_q, bits)
+    np.testing.assert_allclose(amp, ref, atol=1e-12)
+
+
+def test_single_leaf_and_tiny_networks():
+    # one qubit, no gates, open: the amplitude vector is |0>
+    c = Circuit(1, [])
+    plan = tnrcs.Plan(c, [], [], [0], None, dry_run=True)
+    np.testing.assert_allclose(_run_plan(plan, 1, 1), [1, 0])
+    # one qubit, one gate, closed at 1
+    c = Circuit(1, [Gate("sqrt_x", (0,), (), oracle.sqrt_x())])
+    plan = tnrcs.Plan(c, [(0, 1), (3, 2)], [], [], [1], dry_run=True)
+    np.testing.assert_allclose(_run_plan(plan, 1, 0), [-1j / np.sqrt(2)], atol=1e-15)
+
+
+def test_set_output_bits_rebinds():
+    c = make_rqc(3, 3, 6, 7)
+    ns = network_structure(c, [4])
+    pairs = bisection_order(ns, seed=0)
+    b1 = random_bitstrings(9, 2, seed=3)
+    plan = tnrcs.Plan(c, pairs, [], [4], b1[0], dry_run=True)
+    np.testing.assert_allclose(_run_plan(plan, 1, 1), oracle.amplitudes_sv(c, [4], b1[0]), atol=1e-12)
+    plan.set_output_bits(b1[1])
+    np.testing.assert_allclose(_run_plan(plan, 1, 1), oracle.amplitudes_sv(c, [4], b1[1]), atol=1e-12)
+
+
+def test_errors():
+    c = make_rqc(2, 2, 4, 0)
+    ns = network_structure(c, [0])
+    pairs = greedy_order(ns, 0)
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Plan(c, pairs[:-1], [], [0], None, dry_run=True)
+    assert e.value.code == -2
+    bad = list(pairs)
+    bad[-1] = (bad[-1][0], bad[-1][0])
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Plan(c, bad, [], [0], None, dry_run=True)
+    assert e.value.code == -2
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Plan(c, pairs, [ns.open_wires[0]], [0], None, dry_run=True)
+    assert e.value.code == -1
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Plan(c, pairs, [10**6], [0], None, dry_run=True)
+    assert e.value.code == -2
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Plan(c, pairs, [], [0, 0], None, dry_run=True)
+    assert e.value.code == -1
+    plan = tnrcs.Plan(c, pairs, [], [0], None, dry_run=True)
+    with pytest.raises(tnrcs.TnError) as e:
+        plan.contract(0, 1, 0, stream=0)
+    assert e.value.code == -5
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tnrcs.h")).read()
+    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(tn_\w+)\s*\(", header, flags=re.M))
+    assert len(declared) >= 15
+    lib = ctypes.CDLL(tnrcs.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(tnrcs.EXPORTED)
