@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "sec/slice + complex TFLOP/s (% MFMA peak), 53-qubit 14-cycle synthetic RCS"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0       # GB/s
-KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 9: "k_accum"}
+KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 4: "k_splitk", 9: "k_accum"}
 
 
 def log(*a):
@@ -149,6 +149,14 @@ def main():
         kernel_split["k_permute"]["GB/s"] = perm["bytes"] / (perm["ms"] / 1e3) / 1e9
         kernel_split["k_permute"]["frac_hbm"] = kernel_split["k_permute"]["GB/s"] / PEAK_HBM
     log(f"[bench] per-kernel: {json.dumps(kernel_split)}")
+    order = sorted(range(len(ops)), key=lambda i: -ms[i])
+    for i in order[:16]:
+        o = ops[i]
+        shape = (f"M={o['M']} N={o['N']} K={o['K']}" if o["kind"] == 1 else
+                 f"rank={o['rank']}" if o["kind"] == 0 else f"nM={o['nM']} nN={o['nN']} nK={o['nK']}")
+        rate = (f"{o['flops'] / (ms[i] / 1e3) / 1e12:.1f} TFLOP/s" if o["kind"] == 1 else
+                f"{o['bytes'] / (ms[i] / 1e3) / 1e9:.0f} GB/s")
+        log(f"[bench]   op {i:3d} {KIND_NAMES.get(o['kind'], o['kind']):10s} {ms[i]:9.3f} ms  {shape:28s} {rate}")
 
     cpu = None
     if not args.no_cpu_baseline:

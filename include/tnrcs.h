@@ -182,14 +182,18 @@ const char* tn_last_error(void);
 int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm, int64_t batch,
                    void* stream);
 
-/* Complex GEMM from real MFMA products with FP32 accumulation:
+/* Complex GEMM from real MFMA products with FP32 accumulation (the matrix
+ * product of Supplement Eq. (matmul)):
  * C[m][n] = sum_k A[m][k] * B[n][k] for `batch` independent problems
  * (complex64, row-major, A: M x K, B: N x K, C: M x N, batch strides
  * M*K, N*K, M*N elements).  form = TN_GEMM_4M or TN_GEMM_3M.  M, N multiples
  * of 64 and K a multiple of 16 (the planner only emits such shapes; other
- * shapes are routed to the other kernels). */
+ * shapes are routed to the other kernels).  splits > 1 (batch 1, M and N
+ * multiples of 128, K a multiple of 16*splits) splits K into slabs written to
+ * `work` (device, splits*M*N complex64, caller-owned) and summed in slab
+ * order; work may be NULL when splits <= 1. */
 int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
-                 int64_t batch, int32_t form, void* stream);
+                 int64_t batch, int32_t form, void* work, int32_t splits, void* stream);
 
 /* FP64 reductions over an amplitude buffer (complex128, device):
  *  out[0] = sum |a|^2 over n entries (the norm of an all-open run). */

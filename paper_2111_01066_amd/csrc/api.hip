@@ -74,6 +74,31 @@ static int upload_leaves(tn_plan_s* p) {
   return TN_OK;
 }
 
+// Launches the kernel(s) of one planned op.
+static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
+  const float2* a = resolve(p, op.a);
+  const float2* b = resolve(p, op.b);
+  float2* c = const_cast<float2*>(resolve(p, op.c));
+  switch (op.kind) {
+    case kOpPermute:
+      HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
+      break;
+    case kOpGemm:
+      HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s,
+                              op.gemm.split_k > 1 ? const_cast<float2*>(resolve(p, op.w)) : nullptr,
+                              op.gemm.split_k),
+              "gemm kernel");
+      break;
+    case kOpSplitK:
+      HIP_TRY(launch_splitk_c64(a, b, c, const_cast<float2*>(resolve(p, op.w)), op.idx, s), "split-K kernel");
+      break;
+    default:
+      HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
+      break;
+  }
+  return TN_OK;
+}
+
 // Enqueues one slice: bind, the per-step kernels, FP64 accumulation.
 static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
   const PlanCore& P = p->core;
@@ -81,20 +106,8 @@ static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
     HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
             "bind kernel");
   for (const Op& op : P.ops) {
-    const float2* a = resolve(p, op.a);
-    const float2* b = resolve(p, op.b);
-    float2* c = const_cast<float2*>(resolve(p, op.c));
-    switch (op.kind) {
-      case kOpPermute:
-        HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
-        break;
-      case kOpGemm:
-        HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s), "gemm kernel");
-        break;
-      default:
-        HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
-        break;
-    }
+    int rc = launch_op(p, op, s);
+    if (rc) return rc;
   }
   HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
   return TN_OK;
@@ -287,22 +300,9 @@ int tn_plan_profile(tn_plan_t p, int64_t slice, void* amp, void* stream, float* 
       HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
               "bind kernel");
     for (int i = 0; i < (int)P.ops.size(); ++i) {
-      const Op& op = P.ops[i];
-      const float2* a = resolve(p, op.a);
-      const float2* b = resolve(p, op.b);
-      float2* c = const_cast<float2*>(resolve(p, op.c));
       HIP_TRY(hipEventRecord(ev[i], s), "event record");
-      switch (op.kind) {
-        case kOpPermute:
-          HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
-          break;
-        case kOpGemm:
-          HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s), "gemm kernel");
-          break;
-        default:
-          HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
-          break;
-      }
+      int rc2 = launch_op(p, P.ops[i], s);
+      if (rc2) return rc2;
     }
     HIP_TRY(hipEventRecord(ev[nk - 1], s), "event record");
     HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
@@ -392,13 +392,15 @@ int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm,
 }
 
 int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K, int64_t batch,
-                 int32_t form, void* stream) {
+                 int32_t form, void* work, int32_t splits, void* stream) {
   if (!A || !B || !C) return fail(TN_E_ARG, "NULL argument");
   if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
   if (!gemm_shape_ok(M, N, K) || batch < 0)
     return fail(TN_E_ARG, "shape not supported: M, N multiples of 64, K a multiple of 16");
+  if (splits > 1 && (!work || batch != 1 || M % 128 || N % 128 || K % (16 * (int64_t)splits)))
+    return fail(TN_E_ARG, "split-K needs work, batch 1, M and N multiples of 128, K a multiple of 16*splits");
   hipError_t e = launch_gemm_c64((const float2*)A, (const float2*)B, (float2*)C, M, N, K, batch, form,
-                                 (hipStream_t)stream);
+                                 (hipStream_t)stream, (float2*)work, splits < 1 ? 1 : splits);
   if (e != hipSuccess) return hip_fail(e, "gemm kernel");
   return TN_OK;
 }

@@ -32,7 +32,7 @@ struct TRef {
   int64_t off = 0;  // element offset (complex elements) within the region
 };
 
-enum OpKind : int32_t { kOpPermute = 0, kOpGemm = 1, kOpGeneric = 2, kOpSkinny = 3 };
+enum OpKind : int32_t { kOpPermute = 0, kOpGemm = 1, kOpGeneric = 2, kOpSkinny = 3, kOpSplitK = 4 };
 
 // Permute: output position q takes input position perm[q].
 struct PermuteOp {
@@ -61,6 +61,7 @@ struct Op {
   int32_t kind = kOpGeneric;
   int32_t step = -1;  // SSA step this op belongs to
   TRef a, b, c;       // permute: a = in, c = out
+  TRef w;             // workspace (split-K partial sums)
   PermuteOp perm;
   GemmOp gemm;
   IndexOp idx;
@@ -132,6 +133,13 @@ struct PlanCore {
 
 // Planner entry (host only).  Returns TN_OK or an error code with a message.
 int build_plan(PlanCore& P, std::string& err);
+// Blocks of the split-K reduction over 2^nK terms (its workspace holds
+// blocks x outputs entries).
+inline int64_t splitk_grid(int nK) {
+  const int64_t k = (int64_t)1 << nK;
+  const int64_t g = k / 1024;
+  return g < 1 ? 1 : (g > 1024 ? 1024 : g);
+}
 // Re-folds the leaves after an output-bit change (same structure).
 int refold_leaves(PlanCore& P, std::string& err);
 

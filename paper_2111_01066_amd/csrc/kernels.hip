@@ -83,36 +83,55 @@ struct PermArgs {
 
 __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 
+// Tile of 2^TB elements, 256 threads, 2^TB / 256 elements per thread; all of
+// a thread's loads are issued before any LDS store so they are in flight
+// together.  The per-element parts of the offsets that depend only on the
+// unrolled iteration are tabulated once in LDS.
+template <int TB>
 __global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restrict__ in, float2* __restrict__ out,
                                                          const PermArgs a) {
-  __shared__ float2 tile[(1 << kPermTileBits) + (1 << (kPermTileBits - 4))];
+  constexpr int NT = 1 << TB;
+  constexpr int PER = NT / kPermThreads;
+  __shared__ float2 tile[NT + NT / 16];
+  __shared__ uint64_t hi_in[PER], hi_out[PER];
+  __shared__ int hi_fe[PER];
   const int tid = threadIdx.x;
-  const int nt = 1 << a.tbits;
+  if (tid < PER) {
+    hi_in[tid] = dep((uint64_t)tid * kPermThreads, a.in_tile);
+    hi_out[tid] = dep((uint64_t)tid * kPermThreads, a.out_tile);
+    hi_fe[tid] = (int)dep((uint64_t)tid * kPermThreads, a.f2e);
+  }
   const float2* src = in + (int64_t)blockIdx.y * a.stride;
   float2* dst = out + (int64_t)blockIdx.y * a.stride;
   const uint64_t e_t = dep((uint64_t)tid, a.in_tile);
   const uint64_t f_t = dep((uint64_t)tid, a.out_tile);
-  const uint64_t fe_t = dep((uint64_t)tid, a.f2e);
+  const int fe_t = (int)dep((uint64_t)tid, a.f2e);
+  __syncthreads();
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-    const uint64_t ib = dep((uint64_t)t, a.id_in);
-    const uint64_t ob = dep((uint64_t)t, a.id_out);
-    for (int i = 0; i < nt; i += kPermThreads) {
-      const int e = i + tid;
-      if (e < nt) {
-        const uint64_t off = ib | e_t | dep((uint64_t)i, a.in_tile);
-        tile[lds_pad(e)] = src[off];
-      }
-    }
+    const uint64_t ib = dep((uint64_t)t, a.id_in) | e_t;
+    const uint64_t ob = dep((uint64_t)t, a.id_out) | f_t;
+    float2 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) v[i] = src[ib | hi_in[i]];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) tile[lds_pad(i * kPermThreads + tid)] = v[i];
     __syncthreads();
-    for (int i = 0; i < nt; i += kPermThreads) {
-      const int f = i + tid;
-      if (f < nt) {
-        const uint64_t off = ob | f_t | dep((uint64_t)i, a.out_tile);
-        const int e = (int)(fe_t | dep((uint64_t)i, a.f2e));
-        dst[off] = tile[lds_pad(e)];
-      }
-    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) v[i] = tile[lds_pad(fe_t | hi_fe[i])];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) dst[ob | hi_out[i]] = v[i];
     __syncthreads();
+  }
+}
+
+// Tensors below 256 elements: one element per thread, direct gather.
+__global__ __launch_bounds__(256) void k_permute_small(const float2* __restrict__ in, float2* __restrict__ out,
+                                                      const PermArgs a) {
+  const int64_t n = (int64_t)1 << a.tbits;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const float2* src = in + (int64_t)blockIdx.y * a.stride;
+    float2* dst = out + (int64_t)blockIdx.y * a.stride;
+    dst[dep((uint64_t)e, a.out_tile)] = src[dep((uint64_t)e, a.f2e)];
   }
 }
 
@@ -123,6 +142,21 @@ hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int
   for (int q = 0; q < rank; ++q) {
     if (perm[q] < 0 || perm[q] >= rank || inv[perm[q]] >= 0) return hipErrorInvalidValue;
     inv[perm[q]] = q;
+  }
+  if (batch <= 0) return hipSuccess;
+  if (batch > 65535) return hipErrorInvalidValue;
+  PermArgs A{};
+  A.stride = (int64_t)1 << rank;
+  if (rank < 8) {
+    // out index f: output position q holds input bit perm[q]
+    std::vector<int> po, pi;
+    for (int q = 0; q < rank; ++q) po.push_back(q);
+    for (int q = 0; q < rank; ++q) pi.push_back(perm[q]);
+    A.tbits = rank;
+    A.n_tiles = 1;
+    if (!make_runs(po, &A.out_tile) || !make_runs(pi, &A.f2e)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_permute_small, dim3(1, (unsigned)batch), dim3(256), 0, s, in, out, A);
+    return hipGetLastError();
   }
   // choose the tile: grow input-fast and output-fast bit sets alternately
   std::vector<bool> inT(rank, false);
@@ -152,10 +186,8 @@ hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int
   for (int p = 0; p < rank; ++p) (inT[p] ? Tin : R).push_back(p);
   Tout = Tin;
   std::sort(Tout.begin(), Tout.end(), [&](int x, int y) { return inv[x] < inv[y]; });
-  PermArgs A{};
   A.tbits = (int)Tin.size();
   A.n_tiles = (int64_t)1 << (rank - A.tbits);
-  A.stride = (int64_t)1 << rank;
   std::vector<int> p1, p2, p3, p4, p5;
   for (int p : Tin) p1.push_back(p);
   for (int p : Tout) p2.push_back(inv[p]);
@@ -165,9 +197,27 @@ hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int
   if (!make_runs(p1, &A.in_tile) || !make_runs(p2, &A.out_tile) || !make_runs(p3, &A.f2e) ||
       !make_runs(p4, &A.id_in) || !make_runs(p5, &A.id_out))
     return hipErrorInvalidValue;
-  int64_t grid = std::min<int64_t>(A.n_tiles, 8192);
-  if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)grid, (unsigned)batch), dim3(kPermThreads), 0, s, in, out, A);
+  const int64_t grid = std::min<int64_t>(A.n_tiles, 16384);
+  const dim3 g((unsigned)grid, (unsigned)batch);
+  switch (A.tbits) {
+    case 8:
+      hipLaunchKernelGGL(k_permute<8>, g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 9:
+      hipLaunchKernelGGL(k_permute<9>, g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 10:
+      hipLaunchKernelGGL(k_permute<10>, g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 11:
+      hipLaunchKernelGGL(k_permute<11>, g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 12:
+      hipLaunchKernelGGL(k_permute<12>, g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -256,14 +306,165 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
   }
 }
 
+// 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32 MFMA
+// tiles), K staged through LDS 16 at a time; the next K tile is loaded into
+// registers while the current one is multiplied.  Planar LDS: re, im (and,
+// for 3M, re+im formed once per element when the tile is stored).  blockIdx.z
+// selects a batch entry or a split-K slab through the strides sA, sB, sC.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
+                                                 float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
+                                                 int64_t sA, int64_t sB, int64_t sC) {
+  constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
+  constexpr int BM = 128, BN = 128, BK = 16, LD = BM + 2;
+  __shared__ float As[P][BK][LD];
+  __shared__ float Bs[P][BK][LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t bm = (int64_t)blockIdx.x * BM, bn = (int64_t)blockIdx.y * BN;
+  const int64_t z = blockIdx.z;
+  A += z * sA;
+  B += z * sB;
+  C += z * sC;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  floatx16 acc[P][2][2];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = floatx16{};
+  const int lrow = tid >> 1, lk = (tid & 1) * 8;
+  const float2* Ap = A + (bm + lrow) * K + lk;
+  const float2* Bp = B + (bn + lrow) * K + lk;
+  float4 ra[4], rb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ra[j] = *reinterpret_cast<const float4*>(Ap + 2 * j);
+    rb[j] = *reinterpret_cast<const float4*>(Bp + 2 * j);
+  }
+  const int c = lane & 31, kh = lane >> 5;
+  for (int64_t k0 = 0; k0 < k_len; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[0][lk + 2 * j][lrow] = ra[j].x;
+      As[1][lk + 2 * j][lrow] = ra[j].y;
+      As[0][lk + 2 * j + 1][lrow] = ra[j].z;
+      As[1][lk + 2 * j + 1][lrow] = ra[j].w;
+      Bs[0][lk + 2 * j][lrow] = rb[j].x;
+      Bs[1][lk + 2 * j][lrow] = rb[j].y;
+      Bs[0][lk + 2 * j + 1][lrow] = rb[j].z;
+      Bs[1][lk + 2 * j + 1][lrow] = rb[j].w;
+      if (P == 3) {
+        As[P - 1][lk + 2 * j][lrow] = ra[j].x + ra[j].y;
+        As[P - 1][lk + 2 * j + 1][lrow] = ra[j].z + ra[j].w;
+        Bs[P - 1][lk + 2 * j][lrow] = rb[j].x + rb[j].y;
+        Bs[P - 1][lk + 2 * j + 1][lrow] = rb[j].z + rb[j].w;
+      }
+    }
+    __syncthreads();
+    if (k0 + BK < k_len) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ra[j] = *reinterpret_cast<const float4*>(Ap + k0 + BK + 2 * j);
+        rb[j] = *reinterpret_cast<const float4*>(Bp + k0 + BK + 2 * j);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int kr = kk + kh;
+      float a[P][2], b[P][2];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[p][i] = As[p][kr][wm + 32 * i + c];
+          b[p][i] = Bs[p][kr][wn + 32 * i + c];
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (FORM == TN_GEMM_3M) {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][i], b[1][j], acc[1][i][j], 0, 0, 0);
+            acc[P - 1][i][j] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[P - 1][i], b[P - 1][j], acc[P - 1][i][j], 0, 0, 0);
+          } else {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][i], b[1][j], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[1][j], acc[1][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][i], b[0][j], acc[1][i][j], 0, 0, 0);
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int col = wn + 32 * j + c;
+        float2 v;
+        if (FORM == TN_GEMM_3M) {
+          v.x = acc[0][i][j][r] - acc[1][i][j][r];
+          v.y = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
+        } else {
+          v.x = acc[0][i][j][r];
+          v.y = acc[1][i][j][r];
+        }
+        C[(bm + row) * N + bn + col] = v;
+      }
+}
+
+// C[i] = sum over slabs s (in order) of W[s][i].
+__global__ __launch_bounds__(256) void k_splitk_sum(const float2* __restrict__ W, float2* __restrict__ C, int64_t n,
+                                                   int slabs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float r = 0.f, im = 0.f;
+    for (int sl = 0; sl < slabs; ++sl) {
+      const float2 v = W[(int64_t)sl * n + i];
+      r += v.x;
+      im += v.y;
+    }
+    C[i] = make_float2(r, im);
+  }
+}
+
 bool gemm_shape_ok(int64_t M, int64_t N, int64_t K) {
   return M > 0 && N > 0 && K > 0 && M % GBM == 0 && N % GBN == 0 && K % GBK == 0;
 }
 
 hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
-                           int64_t batch, int form, hipStream_t s) {
+                           int64_t batch, int form, hipStream_t s, float2* work, int splits) {
   if (!gemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
+  if (splits < 1) splits = 1;
+  const bool big = (M % 128 == 0) && (N % 128 == 0);
+  if (splits > 1) {
+    if (batch != 1 || !work || !big || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
+    const int64_t kl = K / splits;
+    dim3 grid((unsigned)(M / 128), (unsigned)(N / 128), (unsigned)splits);
+    if (form == TN_GEMM_3M)
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N);
+    else
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N);
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
+                       work, C, n, splits);
+    return hipGetLastError();
+  }
+  if (batch > 65535) return hipErrorInvalidValue;
+  if (big) {
+    dim3 grid((unsigned)(M / 128), (unsigned)(N / 128), (unsigned)batch);
+    if (form == TN_GEMM_3M)
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N);
+    else
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)batch);
   if (form == TN_GEMM_3M)
     hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
@@ -300,6 +501,106 @@ hipError_t launch_generic_c64(const float2* A, const float2* B, float2* C, const
   const int64_t nC = (int64_t)1 << (op.nM + op.nN);
   int64_t grid = std::min<int64_t>((nC + 255) / 256, 16384);
   hipLaunchKernelGGL(k_generic, dim3((unsigned)grid), dim3(256), 0, s, A, B, C, op);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- split-K --
+// Few outputs (<= 64) and a long contraction: the K range is split over a
+// fixed grid; each thread accumulates all outputs over its k's (consecutive
+// threads take consecutive k, so the gathers are coalesced wherever the low
+// K bits are the operands' low bits), the block reduces in LDS, and one
+// block sums the per-block partials in a fixed order.
+
+template <int NOUT>
+__global__ __launch_bounds__(256) void k_splitk_part(const float2* __restrict__ A, const float2* __restrict__ B,
+                                                    float2* __restrict__ part, const IndexOp op) {
+  __shared__ uint64_t am[NOUT], bn[NOUT];
+  __shared__ float red[2][256];
+  const int nout = 1 << (op.nM + op.nN);
+  const uint64_t nmask = (1ull << op.nN) - 1ull;
+  const int tid = threadIdx.x;
+  if (tid < nout) {
+    am[tid] = dep((uint64_t)tid >> op.nN, op.aM);
+    bn[tid] = dep((uint64_t)tid & nmask, op.bN);
+  }
+  __syncthreads();
+  float acc_r[NOUT], acc_i[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) acc_r[o] = acc_i[o] = 0.f;
+  const int64_t nK = (int64_t)1 << op.nK;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + tid; k < nK; k += (int64_t)gridDim.x * 256) {
+    const uint64_t ak = dep((uint64_t)k, op.aK), bk = dep((uint64_t)k, op.bK);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      if (o < nout) {
+        const float2 x = A[am[o] | ak];
+        const float2 y = B[bn[o] | bk];
+        acc_r[o] = fmaf(x.x, y.x, acc_r[o]);
+        acc_r[o] = fmaf(-x.y, y.y, acc_r[o]);
+        acc_i[o] = fmaf(x.x, y.y, acc_i[o]);
+        acc_i[o] = fmaf(x.y, y.x, acc_i[o]);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    if (o < nout) {  // uniform across the block
+      red[0][tid] = acc_r[o];
+      red[1][tid] = acc_i[o];
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+          red[0][tid] += red[0][tid + w];
+          red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) part[(int64_t)blockIdx.x * nout + o] = make_float2(red[0][0], red[1][0]);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__ part, int nblk, int nout,
+                                                     float2* __restrict__ C) {
+  __shared__ float red[2][256];
+  const int tid = threadIdx.x;
+  for (int o = 0; o < nout; ++o) {
+    float r = 0.f, i = 0.f;
+    for (int g = tid; g < nblk; g += 256) {
+      const float2 v = part[(int64_t)g * nout + o];
+      r += v.x;
+      i += v.y;
+    }
+    red[0][tid] = r;
+    red[1][tid] = i;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] += red[0][tid + w];
+        red[1][tid] += red[1][tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) C[o] = make_float2(red[0][0], red[1][0]);
+    __syncthreads();
+  }
+}
+
+int64_t splitk_blocks(const IndexOp& op) { return splitk_grid(op.nK); }
+
+hipError_t launch_splitk_c64(const float2* A, const float2* B, float2* C, float2* part, const IndexOp& op,
+                             hipStream_t s) {
+  const int nout = 1 << (op.nM + op.nN);
+  if (nout > 64) return hipErrorInvalidValue;
+  const int64_t g = splitk_blocks(op);
+  if (nout <= 4)
+    hipLaunchKernelGGL(k_splitk_part<4>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+  else if (nout <= 16)
+    hipLaunchKernelGGL(k_splitk_part<16>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+  else
+    hipLaunchKernelGGL(k_splitk_part<64>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+  hipLaunchKernelGGL(k_splitk_final, dim3(1), dim3(256), 0, s, part, (int)g, nout, C);
   return hipGetLastError();
 }
 

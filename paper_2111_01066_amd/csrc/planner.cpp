@@ -513,6 +513,20 @@ int build_plan(PlanCore& P, std::string& err) {
       g.gemm.K = (int64_t)1 << nK;
       g.gemm.form = P.opts.gemm_form == TN_GEMM_3M ? TN_GEMM_3M : TN_GEMM_4M;
       int gi = (int)P.ops.size();
+      // split K when the output has too few 128x128 tiles to fill the chip
+      if (nM >= 7 && nN >= 7) {
+        const int64_t tiles = (int64_t)1 << (nM - 7 + nN - 7);
+        int sp = 1;
+        while (tiles * sp < 2048 && ((int64_t)1 << nK) / (sp * 2) >= 1024 && sp < 64 &&
+               ((int64_t)sp * 2 << (nM + nN)) <= ((int64_t)1 << 28))
+          sp *= 2;
+        if (sp > 1) {
+          g.gemm.split_k = sp;
+          Buf wb{(int64_t)sp << (nM + nN), dstep, dstep, -1, (int)bufs.size()};
+          fix.push_back({gi, 3, (int)bufs.size()});
+          bufs.push_back(wb);
+        }
+      }
       if (a_tmp >= 0)
         fix.push_back({gi, 0, a_tmp});
       else
@@ -530,7 +544,8 @@ int build_plan(PlanCore& P, std::string& err) {
       P.stats.n_dense++;
     } else {
       Op g;
-      g.kind = kOpGeneric;
+      const bool splitk = (nM + nN) <= 6 && nK >= 10;
+      g.kind = splitk ? kOpSplitK : kOpGeneric;
       g.step = t;
       g.idx.nM = nM;
       g.idx.nN = nN;
@@ -557,6 +572,11 @@ int build_plan(PlanCore& P, std::string& err) {
       g.a = operand_ref(ia, gi, 0);
       g.b = operand_ref(ib, gi, 1);
       fix.push_back({gi, 2, cbuf});
+      if (splitk) {
+        Buf wb{splitk_grid(nK) << (nM + nN), dstep, dstep, -1, (int)bufs.size()};
+        fix.push_back({gi, 3, (int)bufs.size()});
+        bufs.push_back(wb);
+      }
       g.flops = 8.0 * std::ldexp(1.0, nM + nN + nK);
       g.bytes = 8.0 * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rcn));
       P.ops.push_back(g);
@@ -573,8 +593,10 @@ int build_plan(PlanCore& P, std::string& err) {
       op.a = r;
     else if (f.which == 1)
       op.b = r;
-    else
+    else if (f.which == 2)
       op.c = r;
+    else
+      op.w = r;
   }
   for (auto& op : P.ops) P.stats.moved_per_slice += op.bytes;
   // final accumulation
@@ -648,7 +670,9 @@ int build_plan(PlanCore& P, std::string& err) {
       for (int q = 0; q < op.perm.rank; ++q) js << (q ? "," : "") << op.perm.perm[q];
       js << "]";
     } else if (op.kind == kOpGemm) {
-      js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form;
+      js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
+         << ",\"split_k\":" << op.gemm.split_k << ",\"w\":";
+      json_ref(js, op.w);
     } else {
       js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
       json_runs(js, op.idx.aM);
@@ -658,7 +682,8 @@ int build_plan(PlanCore& P, std::string& err) {
       json_runs(js, op.idx.bN);
       js << ",\"bK\":";
       json_runs(js, op.idx.bK);
-      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK;
+      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK << ",\"w\":";
+      json_ref(js, op.w);
     }
     js << "}";
   }

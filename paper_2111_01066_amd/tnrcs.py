@@ -78,7 +78,7 @@ _lib.tn_plan_profile.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, POINTER(
                                  POINTER(c_int32)]
 _lib.tn_permute_c64.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32), c_int64, c_void_p]
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
-                              c_void_p]
+                              c_void_p, c_int32, c_void_p]
 _lib.tn_amp_norm2.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_xeb.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_void_p, c_void_p]
@@ -260,9 +260,11 @@ def tn_permute_c64(inp, out, perm: Sequence[int], batch: int = 1, stream=None):
                                c_void_p(_stream(stream))))
 
 
-def tn_cgemm_c64(A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4m", stream=None):
+def tn_cgemm_c64(A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4m", work=None, splits: int = 1,
+                 stream=None):
     _check(_lib.tn_cgemm_c64(c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(M), int(N), int(K),
-                             int(batch), GEMM_FORMS[form], c_void_p(_stream(stream))))
+                             int(batch), GEMM_FORMS[form], c_void_p(_ptr(work) if work is not None else None),
+                             int(splits), c_void_p(_stream(stream))))
 
 
 def tn_amp_norm2(amp, n: int, out, stream=None):

@@ -97,19 +97,22 @@ def test_sliced_sum_and_split_ranges(c1, S, open_q):
     plan.close()
 
 
-def test_deeper_circuit_dense_steps():
-    c = make_rqc(4, 5, 12, seed=5)
-    open_q = list(range(20))
+@pytest.mark.parametrize("d,open_q,S", [(12, list(range(20)), 24), (12, [], 22), (10, [0, 1, 2, 3, 4, 5], 20)])
+def test_deeper_circuit_dense_and_splitk_steps(d, open_q, S):
+    c = make_rqc(4, 5, d, seed=5)
+    bits = random_bitstrings(20, 1, seed=8)[0]
     ns = network_structure(c, open_q)
     pairs = bisection_order(ns, seed=0)
-    sliced = slice_to_fit(ns, pairs, 24)
-    plan = tnrcs.Plan(c, pairs, sliced, open_q, None)
+    sliced = slice_to_fit(ns, pairs, S)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits)
     info = plan.info()
+    kinds = [o["kind"] for o in plan.json()["ops"]]
     assert info["n_dense"] > 0
-    print(f"deep C1-like dense={info['n_dense']} k={len(sliced)}", flush=True)
-    amp = _amps(plan, 20, [(0, info["n_slices"])])
-    psi = oracle.statevector(c).reshape(-1)
-    assert oracle.relative_error_norm(amp, psi) < TOL_C64
+    print(f"4x5 d={d} open={len(open_q)} dense={info['n_dense']} splitk={kinds.count(4)} k={len(sliced)}",
+          flush=True)
+    amp = _amps(plan, len(open_q), [(0, info["n_slices"])])
+    ref = oracle.amplitudes_sv(c, open_q, bits)
+    assert oracle.relative_error_norm(amp, ref) < TOL_C64
     plan.close()
 
 

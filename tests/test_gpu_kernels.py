@@ -50,7 +50,8 @@ def test_permute_rejects_bad_perm():
 
 @pytest.mark.parametrize("form", ["4m", "3m"])
 @pytest.mark.parametrize("M,N,K,batch", [(64, 64, 16, 1), (128, 64, 48, 2), (256, 192, 512, 1),
-                                         (64, 512, 4096, 1)])
+                                         (64, 512, 4096, 1), (128, 128, 16, 1), (256, 384, 1024, 2),
+                                         (512, 256, 4096, 1)])
 def test_cgemm_matches_fp64(form, M, N, K, batch):
     rng = np.random.default_rng(M + N + K)
     A = _rand_c64(rng, batch, M, K)
@@ -65,6 +66,26 @@ def test_cgemm_matches_fp64(form, M, N, K, batch):
     # FP32 accumulation over K terms: normwise error ~ sqrt(K) * 2^-24 relative
     err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
     assert err < 4e-7 * np.sqrt(K) + 1e-6, err
+
+
+@pytest.mark.parametrize("form", ["4m", "3m"])
+@pytest.mark.parametrize("M,N,K,splits", [(128, 128, 4096, 4), (256, 128, 65536, 16), (128, 256, 2048, 8)])
+def test_cgemm_split_k(form, M, N, K, splits):
+    rng = np.random.default_rng(M * 7 + K)
+    A = _rand_c64(rng, M, K)
+    B = _rand_c64(rng, N, K)
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    dA, dB = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    dC = torch.empty((M, N), dtype=torch.complex64, device=DEV)
+    work = torch.empty((splits, M, N), dtype=torch.complex64, device=DEV)
+    print(f"cgemm split-K {form} M={M} N={N} K={K} splits={splits}", flush=True)
+    tnrcs.tn_cgemm_c64(dA, dB, dC, M, N, K, 1, form, work=work, splits=splits)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    assert err < 4e-7 * np.sqrt(K) + 1e-6, err
+    with pytest.raises(tnrcs.TnError):
+        tnrcs.tn_cgemm_c64(dA, dB, dC, M, N, K, 1, form, work=None, splits=splits)
 
 
 def test_cgemm_rejects_bad_shape():
