@@ -511,7 +511,9 @@ int build_plan(PlanCore& P, std::string& err) {
       g.gemm.M = (int64_t)1 << nM;
       g.gemm.N = (int64_t)1 << nN;
       g.gemm.K = (int64_t)1 << nK;
-      g.gemm.form = P.opts.gemm_form == TN_GEMM_3M ? TN_GEMM_3M : TN_GEMM_4M;
+      // auto: the 3M form (three real products per complex product) is the
+      // faster one on every compute-bound shape measured; 4M on request
+      g.gemm.form = P.opts.gemm_form == TN_GEMM_4M ? TN_GEMM_4M : TN_GEMM_3M;
       int gi = (int)P.ops.size();
       // split K when the output has too few 128x128 tiles to fill the chip
       if (nM >= 7 && nN >= 7) {
