@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="auto", choices=["auto", "4m", "3m"])
+    ap.add_argument("--dtype", default="c64", choices=["c64", "f16s", "bf16s"])
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sub-log2", type=int, default=26)
@@ -83,7 +84,7 @@ def main():
     log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
     t0 = time.perf_counter()
     plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, gemm_form=args.form,
-                      use_graph=not args.no_graph)
+                      use_graph=not args.no_graph, dtype=args.dtype)
     info = plan.info()
     log(f"[bench] planned in {time.perf_counter() - t0:.2f} s: {info['n_device_steps']} device steps, "
         f"{info['n_kernels']} kernels/slice, arena {info['arena_bytes'] / 2**30:.1f} GiB, "

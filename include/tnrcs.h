@@ -112,7 +112,19 @@ typedef struct {
 } tn_plan_stats;
 
 /* Fills *o with the defaults (complex64, auto GEMM form, graph on, device 0,
- * host folding up to 2^12 entries, automatic arena budget). */
+ * host folding up to 2^12 entries, automatic arena budget).
+ *
+ * Scaled storage (dtype TN_DTYPE_F16S / TN_DTYPE_BF16S; the main text names
+ * mixed precision without a scheme, this is this library's): every device
+ * tensor T holds value * 2^-e_T in the 16-bit format; leaves get e from their
+ * largest component; every contraction accumulates in FP32 and stores its
+ * result shifted by a per-step power of two chosen once, at tn_plan time, by
+ * running slice 0 step by step and bringing each step's largest accumulator
+ * magnitude to 2^12; the slice result is widened to FP64 with its exponent
+ * before the cross-slice sum.  Later slices reuse the shifts; each slice
+ * checks every step's largest stored magnitude and raises TN_FLAG_OVERFLOW
+ * (the format's maximum reached) or TN_FLAG_UNDERFLOW (a step's largest
+ * magnitude fell below 2^-2), read with tn_plan_status. */
 void tn_plan_opts_default(tn_plan_opts* o);
 
 /* Plans the contraction (main text TNC section; Supplement Fig. S2 and the
@@ -174,13 +186,14 @@ const char* tn_last_error(void);
 /* ---- standalone kernels of the hot path (same kernels the plans run) ---- */
 
 /* Binary-index tensor permutation (the index permutation of Supplement
- * Eq. (matmul)): a rank-r tensor with every dimension 2, complex64, row-major
- * (position p = bit p of the linear index, position 0 fastest).  Output
- * position q takes input position perm[q]:  out[sum_q b_{perm[q]} 2^q] =
- * in[sum_p b_p 2^p].  `batch` tensors at strides of 2^r elements.  in/out are
- * device pointers and must not overlap.  0 <= r <= 40. */
-int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm, int64_t batch,
-                   void* stream);
+ * Eq. (matmul)): a rank-r tensor with every dimension 2, row-major (position
+ * p = bit p of the linear index, position 0 fastest), elements of elem_bytes
+ * = 8 (complex64) or 4 (FP16/BF16 pair).  Output position q takes input
+ * position perm[q]:  out[sum_q b_{perm[q]} 2^q] = in[sum_p b_p 2^p].
+ * `batch` (<= 65535) tensors at strides of 2^r elements.  in/out are device
+ * pointers and must not overlap.  0 <= r <= 40. */
+int tn_permute(const void* in, void* out, int32_t elem_bytes, int32_t rank, const int32_t* perm, int64_t batch,
+               void* stream);
 
 /* Complex GEMM from real MFMA products with FP32 accumulation (the matrix
  * product of Supplement Eq. (matmul)):
@@ -194,6 +207,18 @@ int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm,
  * order; work may be NULL when splits <= 1. */
 int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                  int64_t batch, int32_t form, void* work, int32_t splits, void* stream);
+
+/* Complex GEMM on FP16 (dtype TN_DTYPE_F16S) or BF16 (TN_DTYPE_BF16S) matrix
+ * cores with FP32 accumulation, for scaled storage: A, B, C hold (re, im)
+ * pairs of the 16-bit format; C = round(out_scale * A B^T) with the same
+ * shapes, layouts and batch convention as tn_cgemm_c64; M, N multiples of
+ * 128, K a multiple of 16.  If max_out (device float, non-NULL) is given, the
+ * largest |component| of A B^T (before scaling) is folded into it with an
+ * atomic maximum (it must start at 0 or a smaller value).  splits > 1 as in
+ * tn_cgemm_c64 (work: splits*M*N complex64 entries). */
+int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                  int64_t batch, int32_t form, float out_scale, void* work, int32_t splits, void* max_out,
+                  void* stream);
 
 /* FP64 reductions over an amplitude buffer (complex128, device):
  *  out[0] = sum |a|^2 over n entries (the norm of an all-open run). */

@@ -1,8 +1,11 @@
 // C ABI of the tnrcs library: plan objects, the per-slice scheduler (one HIP
-// graph replay per slice, FP64 accumulation into the caller's buffer) and the
-// standalone kernel entry points.  See include/tnrcs.h for the contract.
+// graph replay per slice, FP64 accumulation into the caller's buffer), the
+// exponent calibration of scaled half-precision plans, and the standalone
+// kernel entry points.  See include/tnrcs.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -33,16 +36,44 @@ int hip_fail(hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(_e, what); \
   } while (0)
 
+// Round-to-nearest-even encodings of a double in IEEE binary16 and bfloat16.
+uint16_t encode_small_float(double v, int mant_bits, int exp_bias, int exp_max_field) {
+  uint16_t sign = std::signbit(v) ? 0x8000u : 0u;
+  double a = std::fabs(v);
+  if (a == 0) return sign;
+  if (!std::isfinite(a)) return sign | (uint16_t)(exp_max_field << mant_bits);
+  int e;
+  std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
+  int ef = e - 1 + exp_bias;  // biased exponent of the normal encoding
+  if (ef <= 0) {
+    // subnormal: unit 2^(1 - bias - mant_bits)
+    double q = std::nearbyint(std::ldexp(a, exp_bias - 1 + mant_bits));
+    return sign | (uint16_t)q;  // q == 2^mant_bits carries into the smallest normal
+  }
+  double q = std::nearbyint(std::ldexp(a, mant_bits + 1 - e));  // in [2^mant, 2^(mant+1)]
+  if (q >= std::ldexp(1.0, mant_bits + 1)) {
+    q /= 2;
+    ++ef;
+  }
+  if (ef >= exp_max_field) return sign | (uint16_t)(exp_max_field << mant_bits);
+  return sign | (uint16_t)((ef << mant_bits) | ((uint32_t)q - (1u << mant_bits)));
+}
+uint16_t to_f16_bits(double v) { return encode_small_float(v, 10, 15, 31); }
+uint16_t to_bf16_bits(double v) { return encode_small_float(v, 7, 127, 255); }
+
 }  // namespace
 
 struct tn_plan_s {
   PlanCore core;
   int device = 0;
-  float2* d_leaves = nullptr;
-  float2* d_bound = nullptr;
-  float2* d_arena = nullptr;
+  int eb = 8;  // element bytes
+  char* d_leaves = nullptr;
+  char* d_bound = nullptr;
+  char* d_arena = nullptr;
   BindDesc* d_binds = nullptr;
   Ctrl* d_ctrl = nullptr;
+  float* d_maxslots = nullptr;
+  float* d_outscales = nullptr;
   int64_t bind_max = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -51,80 +82,167 @@ struct tn_plan_s {
   bool ran = false;
 };
 
-static const float2* resolve(const tn_plan_s* p, const TRef& r) {
-  switch (r.region) {
-    case kLeaves:
-      return p->d_leaves + r.off;
-    case kBound:
-      return p->d_bound + r.off;
-    default:
-      return p->d_arena + r.off;
-  }
+static char* resolve(const tn_plan_s* p, const TRef& r) {
+  char* base = r.region == kLeaves ? p->d_leaves : (r.region == kBound ? p->d_bound : p->d_arena);
+  return base + r.off * (int64_t)p->eb;
 }
 
 static int upload_leaves(tn_plan_s* p) {
-  const PlanCore& P = p->core;
-  std::vector<float2> host((size_t)P.leaves_elems, make_float2(0.f, 0.f));
+  PlanCore& P = p->core;
+  const int dt = P.opts.dtype;
+  if (dt != TN_DTYPE_C64) leaf_exponents(P);
+  std::vector<uint32_t> h32;
+  std::vector<float2> h64;
+  if (dt == TN_DTYPE_C64)
+    h64.assign((size_t)P.leaves_elems, make_float2(0.f, 0.f));
+  else
+    h32.assign((size_t)P.leaves_elems, 0u);
   for (const DevLeaf& d : P.dev_leaves)
-    for (size_t i = 0; i < d.data.size(); ++i)
-      host[d.stored_off + i] = make_float2((float)d.data[i].real(), (float)d.data[i].imag());
-  if (!host.empty())
-    HIP_TRY(hipMemcpy(p->d_leaves, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice),
-            "upload leaves");
+    for (size_t i = 0; i < d.data.size(); ++i) {
+      const double re = d.data[i].real(), im = d.data[i].imag();
+      if (dt == TN_DTYPE_C64) {
+        h64[d.stored_off + i] = make_float2((float)re, (float)im);
+      } else {
+        const double sc = std::ldexp(1.0, -d.e);
+        uint16_t r = dt == TN_DTYPE_F16S ? to_f16_bits(re * sc) : to_bf16_bits(re * sc);
+        uint16_t m = dt == TN_DTYPE_F16S ? to_f16_bits(im * sc) : to_bf16_bits(im * sc);
+        h32[d.stored_off + i] = (uint32_t)r | ((uint32_t)m << 16);
+      }
+    }
+  const void* src = dt == TN_DTYPE_C64 ? (const void*)h64.data() : (const void*)h32.data();
+  if (P.leaves_elems > 0)
+    HIP_TRY(hipMemcpy(p->d_leaves, src, (size_t)P.leaves_elems * p->eb, hipMemcpyHostToDevice), "upload leaves");
+  return TN_OK;
+}
+
+static int upload_scales(tn_plan_s* p) {
+  PlanCore& P = p->core;
+  if (P.n_slots == 0) return TN_OK;
+  std::vector<float> sc(P.n_slots, 1.f), zero(P.n_slots, 0.f);
+  for (const Op& op : P.ops)
+    if (op.max_slot >= 0) sc[op.max_slot] = (float)std::ldexp(1.0, -op.s_out);
+  HIP_TRY(hipMemcpy(p->d_outscales, sc.data(), sc.size() * sizeof(float), hipMemcpyHostToDevice), "upload scales");
+  HIP_TRY(hipMemcpy(p->d_maxslots, zero.data(), zero.size() * sizeof(float), hipMemcpyHostToDevice),
+          "clear magnitude records");
   return TN_OK;
 }
 
 // Launches the kernel(s) of one planned op.
 static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
-  const float2* a = resolve(p, op.a);
-  const float2* b = resolve(p, op.b);
-  float2* c = const_cast<float2*>(resolve(p, op.c));
+  const int dt = p->core.opts.dtype;
+  const char* a = resolve(p, op.a);
+  const char* b = resolve(p, op.b);
+  char* c = resolve(p, op.c);
+  float* slot = op.max_slot >= 0 ? p->d_maxslots + op.max_slot : nullptr;
+  float2* w = reinterpret_cast<float2*>(resolve(p, op.w));
   switch (op.kind) {
     case kOpPermute:
-      HIP_TRY(launch_permute_c64(a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
+      HIP_TRY(launch_permute(p->eb, a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
       break;
     case kOpGemm:
-      HIP_TRY(launch_gemm_c64(a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s,
-                              op.gemm.split_k > 1 ? const_cast<float2*>(resolve(p, op.w)) : nullptr,
-                              op.gemm.split_k),
-              "gemm kernel");
+      if (dt == TN_DTYPE_C64)
+        HIP_TRY(launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, op.gemm.M, op.gemm.N, op.gemm.K, 1,
+                                op.gemm.form, s, op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k),
+                "gemm kernel");
+      else
+        HIP_TRY(launch_gemm_half(dt, a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s,
+                                 op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.out_scale, slot),
+                "half gemm kernel");
       break;
     case kOpSplitK:
-      HIP_TRY(launch_splitk_c64(a, b, c, const_cast<float2*>(resolve(p, op.w)), op.idx, s), "split-K kernel");
+      HIP_TRY(launch_splitk(dt, a, b, c, w, op.idx, slot, s), "split-K kernel");
       break;
     default:
-      HIP_TRY(launch_generic_c64(a, b, c, op.idx, s), "contraction kernel");
+      HIP_TRY(launch_generic(dt, a, b, c, op.idx, slot, s), "contraction kernel");
       break;
   }
   return TN_OK;
 }
 
-// Enqueues one slice: bind, the per-step kernels, FP64 accumulation.
-static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
+static int launch_bind_slice(tn_plan_s* p, hipStream_t s) {
   const PlanCore& P = p->core;
   if (!P.binds.empty())
-    HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
+    HIP_TRY(launch_bind(p->eb, p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
             "bind kernel");
-  for (const Op& op : P.ops) {
-    int rc = launch_op(p, op, s);
+  return TN_OK;
+}
+
+static int launch_accum_slice(tn_plan_s* p, hipStream_t s) {
+  const PlanCore& P = p->core;
+  HIP_TRY(launch_accum(P.opts.dtype, resolve(p, P.accum.root), P.accum, p->d_ctrl, p->d_maxslots, p->d_outscales,
+                       P.n_slots, s),
+          "accumulate kernel");
+  return TN_OK;
+}
+
+// Enqueues one slice: bind, the per-step kernels, FP64 accumulation.
+static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
+  int rc = launch_bind_slice(p, s);
+  if (rc) return rc;
+  for (const Op& op : p->core.ops) {
+    rc = launch_op(p, op, s);
     if (rc) return rc;
   }
-  HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
-  return TN_OK;
+  return launch_accum_slice(p, s);
+}
+
+// Scaled storage: choose every producing op's output shift from slice 0.  Op
+// by op in plan order: run it with shift 0 (its FP32 accumulator magnitude is
+// recorded before any rounding), derive the shift that brings the largest
+// magnitude to 2^kTargetLog2, run it again so its stored output uses that
+// shift, and go on to the next op (whose inputs are now final).
+static int calibrate(tn_plan_s* p) {
+  PlanCore& P = p->core;
+  if (P.opts.dtype == TN_DTYPE_C64 || P.n_slots == 0) {
+    propagate_exponents(P);
+    return TN_OK;
+  }
+  hipStream_t s = nullptr;
+  HIP_TRY(launch_set_ctrl(p->d_ctrl, 0, nullptr, s), "control kernel");
+  int rc = launch_bind_slice(p, s);
+  if (rc) return rc;
+  const float zero = 0.f;
+  for (Op& op : P.ops) {
+    if (op.max_slot < 0) {
+      if ((rc = launch_op(p, op, s))) return rc;
+      continue;
+    }
+    float* slot = p->d_maxslots + op.max_slot;
+    set_output_shift(op, 0.f);
+    HIP_TRY(hipMemcpy(slot, &zero, sizeof(float), hipMemcpyHostToDevice), "clear record");
+    if ((rc = launch_op(p, op, s))) return rc;
+    float mx = 0.f;
+    HIP_TRY(hipMemcpy(&mx, slot, sizeof(float), hipMemcpyDeviceToHost), "read record");
+    if (!std::isfinite(mx)) return fail(TN_E_NUMERIC, "calibration: non-finite accumulator in step " +
+                                                         std::to_string(op.step));
+    set_output_shift(op, mx);
+    if ((rc = launch_op(p, op, s))) return rc;
+  }
+  HIP_TRY(hipDeviceSynchronize(), "calibration synchronize");
+  propagate_exponents(P);
+  return upload_scales(p);
+}
+
+static void drop_graph(tn_plan_s* p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
 }
 
 static void release(tn_plan_s* p) {
   if (!p) return;
   if (p->core.opts.dry_run) return;
   hipSetDevice(p->device);
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  drop_graph(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   hipFree(p->d_leaves);
   hipFree(p->d_bound);
   hipFree(p->d_arena);
   hipFree(p->d_binds);
   hipFree(p->d_ctrl);
+  hipFree(p->d_maxslots);
+  hipFree(p->d_outscales);
 }
 
 extern "C" {
@@ -159,7 +277,8 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
     o = *opts;
   else
     tn_plan_opts_default(&o);
-  if (o.dtype != TN_DTYPE_C64) return fail(TN_E_UNSUPPORTED, "only complex64 storage is built in this version");
+  if (o.dtype != TN_DTYPE_C64 && o.dtype != TN_DTYPE_F16S && o.dtype != TN_DTYPE_BF16S)
+    return fail(TN_E_ARG, "unknown dtype");
   if (o.host_fold_log2 < 0 || o.host_fold_log2 > 20) return fail(TN_E_ARG, "host_fold_log2 out of range");
   for (int g = 0; g < c->n_gates; ++g) {
     const tn_gate& G = c->gates[g];
@@ -195,7 +314,10 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
     return fail(rc, err);
   }
   p->device = o.device;
+  p->eb = elem_bytes_of(o.dtype);
   if (o.dry_run) {
+    if (o.dtype != TN_DTYPE_C64) leaf_exponents(P);
+    propagate_exponents(P);
     *out = p;
     return TN_OK;
   }
@@ -210,7 +332,7 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) return bail(hip_fail(e, "hipMemGetInfo"));
-  const int64_t need = (P.arena_elems + P.leaves_elems + P.bound_elems) * (int64_t)sizeof(float2);
+  const int64_t need = (P.arena_elems + P.leaves_elems + P.bound_elems) * (int64_t)p->eb;
   const int64_t budget = o.arena_bytes > 0 ? o.arena_bytes : (int64_t)(0.92 * (double)free_b);
   if (need > budget)
     return bail(fail(TN_E_MEM, "plan needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget)));
@@ -220,9 +342,11 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
     if (e2 != hipSuccess) return hip_fail(e2, what);
     return TN_OK;
   };
-  if ((rc = dmalloc((void**)&p->d_leaves, P.leaves_elems * 8, "alloc leaves")) ||
-      (rc = dmalloc((void**)&p->d_bound, P.bound_elems * 8, "alloc bound leaves")) ||
-      (rc = dmalloc((void**)&p->d_arena, P.arena_elems * 8, "alloc arena")) ||
+  if ((rc = dmalloc((void**)&p->d_leaves, P.leaves_elems * p->eb, "alloc leaves")) ||
+      (rc = dmalloc((void**)&p->d_bound, P.bound_elems * p->eb, "alloc bound leaves")) ||
+      (rc = dmalloc((void**)&p->d_arena, P.arena_elems * p->eb, "alloc arena")) ||
+      (rc = dmalloc((void**)&p->d_maxslots, (int64_t)std::max(P.n_slots, 1) * 4, "alloc records")) ||
+      (rc = dmalloc((void**)&p->d_outscales, (int64_t)std::max(P.n_slots, 1) * 4, "alloc scales")) ||
       (rc = dmalloc((void**)&p->d_binds, (int64_t)P.binds.size() * (int64_t)sizeof(BindDesc), "alloc binds")) ||
       (rc = dmalloc((void**)&p->d_ctrl, sizeof(Ctrl), "alloc control")))
     return bail(rc);
@@ -233,6 +357,9 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
     for (auto& b : P.binds) p->bind_max = std::max(p->bind_max, b.n_elems);
   }
   Ctrl zero{};
+  e = hipMemcpy(p->d_ctrl, &zero, sizeof(Ctrl), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(hip_fail(e, "init control"));
+  if ((rc = calibrate(p))) return bail(rc);
   e = hipMemcpy(p->d_ctrl, &zero, sizeof(Ctrl), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(e, "init control"));
   *out = p;
@@ -296,16 +423,16 @@ int tn_plan_profile(tn_plan_t p, int64_t slice, void* amp, void* stream, float* 
   int rc = TN_OK;
   auto body = [&]() -> int {
     HIP_TRY(launch_set_ctrl(p->d_ctrl, slice, amp, s), "control kernel");
-    if (!P.binds.empty())
-      HIP_TRY(launch_bind(p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
-              "bind kernel");
+    int rc1 = launch_bind_slice(p, s);
+    if (rc1) return rc1;
     for (int i = 0; i < (int)P.ops.size(); ++i) {
       HIP_TRY(hipEventRecord(ev[i], s), "event record");
       int rc2 = launch_op(p, P.ops[i], s);
       if (rc2) return rc2;
     }
     HIP_TRY(hipEventRecord(ev[nk - 1], s), "event record");
-    HIP_TRY(launch_accum(resolve(p, P.accum.root), P.accum, p->d_ctrl, s), "accumulate kernel");
+    int rc3 = launch_accum_slice(p, s);
+    if (rc3) return rc3;
     HIP_TRY(hipEventRecord(ev[nk], s), "event record");
     HIP_TRY(hipEventSynchronize(ev[nk]), "event synchronize");
     for (int i = 0; i < nk; ++i) HIP_TRY(hipEventElapsedTime(&op_ms[i], ev[i], ev[i + 1]), "event elapsed");
@@ -368,7 +495,11 @@ int tn_plan_set_output_bits(tn_plan_t p, const uint8_t* out_bits) {
   if (P.opts.dry_run) return TN_OK;
   HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
   if (p->ran) HIP_TRY(hipStreamSynchronize(p->last_stream), "stream synchronize");
-  return upload_leaves(p);
+  rc = upload_leaves(p);
+  if (rc) return rc;
+  propagate_exponents(P);  // leaf exponents may have moved: new root scale
+  drop_graph(p);           // the captured accumulation holds the old scale
+  return TN_OK;
 }
 
 int tn_plan_destroy(tn_plan_t p) {
@@ -382,12 +513,30 @@ int tn_plan_destroy(tn_plan_t p) {
   return TN_OK;
 }
 
-int tn_permute_c64(const void* in, void* out, int32_t rank, const int32_t* perm, int64_t batch, void* stream) {
+int tn_permute(const void* in, void* out, int32_t elem_bytes, int32_t rank, const int32_t* perm, int64_t batch,
+               void* stream) {
   if (!in || !out || !perm) return fail(TN_E_ARG, "NULL argument");
-  if (rank < 0 || rank > 40 || batch < 0) return fail(TN_E_ARG, "rank or batch out of range");
-  hipError_t e = launch_permute_c64((const float2*)in, (float2*)out, rank, perm, batch, (hipStream_t)stream);
+  if (elem_bytes != 4 && elem_bytes != 8) return fail(TN_E_ARG, "elem_bytes must be 4 or 8");
+  if (rank < 0 || rank > 40 || batch < 0 || batch > 65535) return fail(TN_E_ARG, "rank or batch out of range");
+  hipError_t e = launch_permute(elem_bytes, in, out, rank, perm, batch, (hipStream_t)stream);
   if (e == hipErrorInvalidValue) return fail(TN_E_ARG, "perm is not a permutation of 0..rank-1");
   if (e != hipSuccess) return hip_fail(e, "permute kernel");
+  return TN_OK;
+}
+
+int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                  int64_t batch, int32_t form, float out_scale, void* work, int32_t splits, void* max_out,
+                  void* stream) {
+  if (!A || !B || !C) return fail(TN_E_ARG, "NULL argument");
+  if (dtype != TN_DTYPE_F16S && dtype != TN_DTYPE_BF16S) return fail(TN_E_ARG, "dtype must be F16S or BF16S");
+  if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
+  if (!hgemm_shape_ok(M, N, K) || batch < 0 || batch > 65535)
+    return fail(TN_E_ARG, "shape not supported: M, N multiples of 128, K a multiple of 16");
+  if (splits > 1 && (!work || batch != 1 || K % (16 * (int64_t)splits)))
+    return fail(TN_E_ARG, "split-K needs work, batch 1 and K a multiple of 16*splits");
+  hipError_t e = launch_gemm_half(dtype, A, B, C, M, N, K, batch, form, (hipStream_t)stream, (float2*)work,
+                                  splits < 1 ? 1 : splits, out_scale, (float*)max_out);
+  if (e != hipSuccess) return hip_fail(e, "half gemm kernel");
   return TN_OK;
 }
 

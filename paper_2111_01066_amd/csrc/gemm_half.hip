@@ -1,0 +1,292 @@
+// Complex GEMM on FP16 / BF16 matrix cores with FP32 accumulation, for the
+// scaled half-precision storage (the matrix product of Supplement Eq. (matmul)
+// in the mixed-precision mode the main text names).
+//
+// C[m][n] = sum_k A[m][k] B[n][k]: A, B, C are (re, im) pairs of FP16 or BF16
+// holding value * 2^-e.  The FP32 accumulator holds A_st * B_st; the epilogue
+// multiplies by the op's output scale 2^-s before rounding to the storage
+// format, so C's exponent is e_A + e_B + s.  v_mfma_f32_32x32x16_{f16,bf16};
+// 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32), K staged
+// through LDS as planar re / im (and, for 3M, re+im formed in FP32 and rounded
+// once) rows of BK halves; the next K tile is prefetched into registers while
+// the current one is multiplied.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "elem.h"
+#include "kernels.h"
+
+namespace tnrcs {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename H>
+struct Frag;
+template <>
+struct Frag<_Float16> {
+  typedef half8 T;
+  static __device__ __forceinline__ floatx16 mfma(T a, T b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<__bf16> {
+  typedef bf16x8 T;
+  static __device__ __forceinline__ floatx16 mfma(T a, T b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename H>
+__device__ __forceinline__ uint16_t hbits(float x) {
+  H h = (H)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+template <typename H>
+__device__ __forceinline__ float hval(uint32_t bits16) {
+  return (float)__builtin_bit_cast(H, (uint16_t)bits16);
+}
+
+// Stores one K stage (registers -> LDS buffer), deinterleaving (re, im)
+// words into planar rows: two complex words give one 32-bit pair of re halves
+// and one of im halves (v_perm_b32 byte selects).
+template <int P, int BM, int LDK, int NV, typename H>
+__device__ __forceinline__ void store_stage(H (*S)[BM][LDK], const uint4* r, int row, int k0) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const uint32_t w[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
+    const uint32_t re01 = __builtin_amdgcn_perm(w[1], w[0], 0x05040100u);
+    const uint32_t re23 = __builtin_amdgcn_perm(w[3], w[2], 0x05040100u);
+    const uint32_t im01 = __builtin_amdgcn_perm(w[1], w[0], 0x07060302u);
+    const uint32_t im23 = __builtin_amdgcn_perm(w[3], w[2], 0x07060302u);
+    *reinterpret_cast<uint2*>(&S[0][row][k0 + 4 * j]) = make_uint2(re01, re23);
+    *reinterpret_cast<uint2*>(&S[1][row][k0 + 4 * j]) = make_uint2(im01, im23);
+    if (P == 3) {
+      uint32_t sm[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm[q] = hbits<H>(hval<H>(w[q] & 0xFFFFu) + hval<H>(w[q] >> 16));
+      *reinterpret_cast<uint2*>(&S[P - 1][row][k0 + 4 * j]) = make_uint2(sm[0] | (sm[1] << 16), sm[2] | (sm[3] << 16));
+    }
+  }
+}
+
+template <int FORM, int BK, int WT, typename H, typename E>
+__global__ __launch_bounds__(256, 2) void k_hgemm128(const E* __restrict__ A, const E* __restrict__ B,
+                                                 void* __restrict__ Cout, int64_t N, int64_t K, int64_t k_len,
+                                                 int64_t sA, int64_t sB, int64_t sC, float out_scale,
+                                                 float* maxslot, int to_work, int64_t Mt, int64_t Nt) {
+  typedef typename Frag<H>::T F;
+  constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
+  constexpr int BM = 64 * WT, BN = 64 * WT, LDK = BK + 8;
+  constexpr int TPR = 256 / BM;  // threads per operand row
+  constexpr int CPT = BK / TPR;  // complex elements per thread per operand per stage
+  constexpr int NV = CPT / 4;    // uint4 loads per thread per operand
+  // two LDS buffers: the MFMAs read one stage while the next is stored
+  __shared__ __attribute__((aligned(16))) H As[2][P][BM][LDK];
+  __shared__ __attribute__((aligned(16))) H Bs[2][P][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t tm, tn, z;
+  xcd_tile(blockIdx.x, Mt, Nt, gridDim.x, tm, tn, z);
+  const int64_t bm = tm * BM, bn = tn * BN;
+  A += z * sA;
+  B += z * sB;
+  const int wm = (wave & 1) * 32 * WT, wn = (wave >> 1) * 32 * WT;
+  floatx16 acc[P][WT][WT];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int j = 0; j < WT; ++j) acc[p][i][j] = floatx16{};
+  const int lrow = tid / TPR, lk = (tid % TPR) * CPT;
+  const uint4* Ap = reinterpret_cast<const uint4*>(A + (bm + lrow) * K + lk);
+  const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + lrow) * K + lk);
+  uint4 ra[NV], rb[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    ra[j] = Ap[j];
+    rb[j] = Bp[j];
+  }
+  store_stage<P, BM, LDK, NV, H>(As[0], ra, lrow, lk);
+  store_stage<P, BN, LDK, NV, H>(Bs[0], rb, lrow, lk);
+  if (BK < k_len) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      ra[j] = Ap[BK / 4 + j];
+      rb[j] = Bp[BK / 4 + j];
+    }
+  }
+  __syncthreads();
+  const int c = lane & 31, kq = (lane >> 5) * 8;
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < k_len; k0 += BK) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      F a[P][WT], b[P][WT];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+          a[p][i] = *reinterpret_cast<const F*>(&As[cur][p][wm + 32 * i + c][kk + kq]);
+          b[p][i] = *reinterpret_cast<const F*>(&Bs[cur][p][wn + 32 * i + c][kk + kq]);
+        }
+#pragma unroll
+      for (int i = 0; i < WT; ++i) {
+        F na;
+        if (FORM != TN_GEMM_3M) {
+          uint4 t = __builtin_bit_cast(uint4, a[1][i]);
+          t.x ^= 0x80008000u;
+          t.y ^= 0x80008000u;
+          t.z ^= 0x80008000u;
+          t.w ^= 0x80008000u;
+          na = __builtin_bit_cast(F, t);
+        }
+#pragma unroll
+        for (int j = 0; j < WT; ++j) {
+          if (FORM == TN_GEMM_3M) {
+            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+            acc[1][i][j] = Frag<H>::mfma(a[1][i], b[1][j], acc[1][i][j]);
+            acc[P - 1][i][j] = Frag<H>::mfma(a[P - 1][i], b[P - 1][j], acc[P - 1][i][j]);
+          } else {
+            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+            acc[1][i][j] = Frag<H>::mfma(a[0][i], b[1][j], acc[1][i][j]);
+            acc[0][i][j] = Frag<H>::mfma(na, b[1][j], acc[0][i][j]);
+            acc[1][i][j] = Frag<H>::mfma(a[1][i], b[0][j], acc[1][i][j]);
+          }
+        }
+      }
+    }
+    if (k0 + BK < k_len) {
+      store_stage<P, BM, LDK, NV, H>(As[cur ^ 1], ra, lrow, lk);
+      store_stage<P, BN, LDK, NV, H>(Bs[cur ^ 1], rb, lrow, lk);
+      if (k0 + 2 * BK < k_len) {
+        const int64_t adv = (k0 + 2 * BK) / 4;  // uint4 = 4 complex elements
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          ra[j] = Ap[adv + j];
+          rb[j] = Bp[adv + j];
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  float mx = 0.f;
+  const int kh = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < WT; ++i)
+#pragma unroll
+    for (int j = 0; j < WT; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int col = wn + 32 * j + c;
+        float re, im;
+        if (FORM == TN_GEMM_3M) {
+          re = acc[0][i][j][r] - acc[1][i][j][r];
+          im = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
+        } else {
+          re = acc[0][i][j][r];
+          im = acc[1][i][j][r];
+        }
+        const int64_t o = (bm + row) * N + bn + col;
+        if (to_work) {
+          reinterpret_cast<float2*>(Cout)[z * sC + o] = make_float2(re, im);
+        } else {
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+          reinterpret_cast<E*>(Cout)[z * sC + o] = from_f2<E>(re * out_scale, im * out_scale);
+        }
+      }
+  if (!to_work) record_max(maxslot, mx);
+}
+
+// C[i] = (sum over slabs s, in order, of W[s][i]) * scale, rounded to E.
+template <typename E>
+__global__ __launch_bounds__(256) void k_hsplit_sum(const float2* __restrict__ W, E* __restrict__ C, int64_t n,
+                                                   int slabs, float out_scale, float* maxslot) {
+  float mx = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float r = 0.f, im = 0.f;
+    for (int sl = 0; sl < slabs; ++sl) {
+      const float2 v = W[(int64_t)sl * n + i];
+      r += v.x;
+      im += v.y;
+    }
+    mx = fmaxf(mx, fmaxf(fabsf(r), fabsf(im)));
+    C[i] = from_f2<E>(r * out_scale, im * out_scale);
+  }
+  record_max(maxslot, mx);
+}
+
+bool hgemm_shape_ok(int64_t M, int64_t N, int64_t K) {
+  return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % 16 == 0 && (M / 64) * (N / 64) < (1ll << 31);
+}
+
+template <int FORM, typename H, typename E>
+static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, const E* B, void* C, int64_t N, int64_t K,
+                           int64_t kl, int64_t sA, int64_t sB, int64_t sC, float scale, float* maxslot, int to_work) {
+  // short contractions are store-bound: 64x64 tiles keep more workgroups in
+  // flight; otherwise 128x128 tiles with 32-deep K stages
+  if (kl <= 64 || (M % 128) || (N % 128)) {
+    const int64_t Mt = M / 64, Nt = N / 64;
+    const dim3 grid((unsigned)(Mt * Nt * z));
+    if (kl % 32 == 0)
+      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+                         maxslot, to_work, Mt, Nt);
+    else
+      hipLaunchKernelGGL((k_hgemm128<FORM, 16, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+                         maxslot, to_work, Mt, Nt);
+    return;
+  }
+  const int64_t Mt = M / 128, Nt = N / 128;
+  const dim3 grid((unsigned)(Mt * Nt * z));
+  if (kl % 32 == 0)
+    hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+                       maxslot, to_work, Mt, Nt);
+  else
+    hipLaunchKernelGGL((k_hgemm128<FORM, 16, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+                       maxslot, to_work, Mt, Nt);
+}
+
+template <typename H, typename E>
+static hipError_t hgemm_t(const E* A, const E* B, E* C, int64_t M, int64_t N, int64_t K, int64_t batch, int form,
+                          hipStream_t s, float2* work, int splits, float scale, float* maxslot) {
+  if (splits > 1) {
+    const int64_t kl = K / splits;
+    if (form == TN_GEMM_3M)
+      hgemm_dispatch<TN_GEMM_3M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1);
+    else
+      hgemm_dispatch<TN_GEMM_4M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1);
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(k_hsplit_sum<E>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
+                       work, C, n, splits, scale, maxslot);
+    return hipGetLastError();
+  }
+  if (form == TN_GEMM_3M)
+    hgemm_dispatch<TN_GEMM_3M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0);
+  else
+    hgemm_dispatch<TN_GEMM_4M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                            int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
+                            float* maxslot) {
+  if (!hgemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
+  if (batch == 0) return hipSuccess;
+  if (splits < 1) splits = 1;
+  if (splits > 1 && (batch != 1 || !work || K % (16 * splits) != 0 || splits > 65535)) return hipErrorInvalidValue;
+  if (batch > 65535) return hipErrorInvalidValue;
+  if (dtype == TN_DTYPE_F16S)
+    return hgemm_t<_Float16, cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, M, N, K, batch, form, s, work, splits,
+                                   out_scale, maxslot);
+  if (dtype == TN_DTYPE_BF16S)
+    return hgemm_t<__bf16, cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, M, N, K, batch, form, s, work,
+                                  splits, out_scale, maxslot);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tnrcs

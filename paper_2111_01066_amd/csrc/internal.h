@@ -45,6 +45,7 @@ struct GemmOp {
   int64_t M = 0, N = 0, K = 0;
   int32_t form = TN_GEMM_4M;
   int32_t split_k = 1;  // K split into this many partial products (summed in a second pass)
+  float out_scale = 1.f;  // scaled storage: 2^-s applied before rounding
 };
 
 // Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],
@@ -55,6 +56,7 @@ struct IndexOp {
   // skinny tiling (planner-chosen): the tile holds the low tM M-bits and the
   // low tK K-bits of the chunk; the remaining bits index tiles / chunks.
   int32_t tM = 0, tK = 0;
+  float out_scale = 1.f;  // scaled storage: 2^-s applied before rounding
 };
 
 struct Op {
@@ -67,6 +69,12 @@ struct Op {
   IndexOp idx;
   double flops = 0;   // algorithmic (8 per complex MAC)
   double bytes = 0;   // bytes moved by this kernel
+  // scaled storage: producing ops record max |accumulator| in slot max_slot
+  // and store accumulator * 2^-s_out; their result's exponent is
+  // e(ssa_a) + e(ssa_b) + s_out.
+  int32_t max_slot = -1;
+  int32_t s_out = 0;
+  int32_t ssa_a = -1, ssa_b = -1, ssa_c = -1;
 };
 
 // A device leaf: stored once for all slices with its sliced wires as the top
@@ -79,6 +87,7 @@ struct DevLeaf {
   int64_t stored_off = 0;    // element offset in the leaves region
   int64_t bound_off = 0;     // element offset in the bound region (if n_sliced > 0)
   std::vector<std::complex<double>> data;  // FP64 values in the stored layout
+  int32_t e = 0;  // scaled storage: stored = value * 2^-e
 };
 
 struct BindDesc {  // device-side descriptor of one sliced leaf
@@ -92,6 +101,8 @@ struct AccumDesc {
   int32_t n_open = 0;
   Runs y2root;  // amplitude index bits -> root layout positions
   TRef root;
+  int32_t root_ssa = -1;
+  double root_scale = 1.0;  // 2^e_root for scaled storage
 };
 
 struct HostTensor {
@@ -127,6 +138,7 @@ struct PlanCore {
   AccumDesc accum;
   int64_t arena_elems = 0;
   int32_t root_is_leaf = 0;
+  int32_t n_slots = 0;  // producing ops with a magnitude record (scaled storage)
   tn_plan_stats stats{};
   std::string json;
 };
@@ -142,5 +154,13 @@ inline int64_t splitk_grid(int nK) {
 }
 // Re-folds the leaves after an output-bit change (same structure).
 int refold_leaves(PlanCore& P, std::string& err);
+// Scaled storage: leaf exponents from the leaf data (largest |component|
+// brought to 2^kTargetLog2), then every tensor's exponent along the ops and
+// the root scale of the accumulation.
+constexpr int kTargetLog2 = 12;
+void leaf_exponents(PlanCore& P);
+void propagate_exponents(PlanCore& P);
+// Sets op.s_out (and its out_scale) from a recorded max |accumulator|.
+void set_output_shift(Op& op, float max_acc);
 
 }  // namespace tnrcs

@@ -15,20 +15,28 @@ struct Ctrl {
   uint32_t pad;
 };
 
+inline int elem_bytes_of(int dtype) { return dtype == TN_DTYPE_C64 ? 8 : 4; }
+
 hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s);
-hipError_t launch_bind(const float2* leaves, float2* bound, const BindDesc* descs, int n_desc,
+hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,
                        int64_t max_elems, const Ctrl* ctrl, hipStream_t s);
-hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int32_t* perm, int64_t batch,
-                              hipStream_t s);
-// splits > 1: K split into slabs summed in order through `work` (splits*M*N entries).
+hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, const int32_t* perm, int64_t batch,
+                          hipStream_t s);
+// complex64 GEMM on FP32 MFMA; splits > 1: K split into slabs summed in order
+// through `work` (splits*M*N complex64).
 hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
                            int64_t batch, int form, hipStream_t s, float2* work = nullptr, int splits = 1);
-hipError_t launch_generic_c64(const float2* A, const float2* B, float2* C, const IndexOp& op,
-                              hipStream_t s);
-hipError_t launch_splitk_c64(const float2* A, const float2* B, float2* C, float2* part, const IndexOp& op,
-                             hipStream_t s);
+// scaled FP16/BF16 GEMM on half MFMA; C = A B^T * out_scale; max |A B^T| recorded in *maxslot.
+hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                            int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
+                            float* maxslot);
+hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
+                          hipStream_t s);
+hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
+                         float* maxslot, hipStream_t s);
 int64_t splitk_blocks(const IndexOp& op);
-hipError_t launch_accum(const float2* root, const AccumDesc& d, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,
+                        const float* out_scales, int n_slots, hipStream_t s);
 hipError_t launch_norm2(const double* amp, int64_t n, double* out, hipStream_t s);
 hipError_t launch_xeb(const double* amp, int64_t n, const int64_t* idx, int64_t n_idx, double* out,
                       hipStream_t s);
@@ -36,5 +44,6 @@ hipError_t launch_hist(const double* amp, int64_t n, double scale, double xmax, 
                        unsigned long long* counts, hipStream_t s);
 
 bool gemm_shape_ok(int64_t M, int64_t N, int64_t K);
+bool hgemm_shape_ok(int64_t M, int64_t N, int64_t K);
 
 }  // namespace tnrcs

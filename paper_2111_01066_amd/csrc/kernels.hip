@@ -1,6 +1,9 @@
-// gfx950 kernels of the tnrcs library: slice binding, tiled binary-index
-// permutation, complex GEMM from real MFMA products (4M / 3M), generic
-// gathered contraction, FP64 slice accumulation and FP64 reductions.
+// gfx950 kernels of the tnrcs library other than the GEMMs: slice binding,
+// tiled binary-index permutation, gathered contraction (one output per
+// thread, or split over K for few outputs), FP64 slice accumulation with the
+// numeric-range checks of scaled storage, and FP64 reductions.  Every data
+// kernel is templated on the storage element: complex64, or an FP16 / BF16
+// pair holding value * 2^-e for a per-tensor exponent e.
 //
 // Paper anchors: each pairwise contraction is an index permutation followed by
 // a complex matrix product (Supplement Eq. (matmul)); slicing sums smaller
@@ -12,17 +15,10 @@
 #include <cstdio>
 #include <vector>
 
+#include "elem.h"
 #include "kernels.h"
 
 namespace tnrcs {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
-  uint64_t o = 0;
-  for (int i = 0; i < r.n; ++i) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
-  return o;
-}
 
 // ---------------------------------------------------------------- control --
 
@@ -40,25 +36,30 @@ hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s)
 // Copies, for every sliced leaf, the sub-tensor selected by the current slice
 // id (its sliced wires are the leaf's top bits) into the bound-leaf region.
 
-__global__ __launch_bounds__(256) void k_bind(const float2* __restrict__ leaves, float2* __restrict__ bound,
+template <typename E>
+__global__ __launch_bounds__(256) void k_bind(const E* __restrict__ leaves, E* __restrict__ bound,
                                               const BindDesc* __restrict__ descs, const Ctrl* __restrict__ ctrl) {
   const BindDesc& d = descs[blockIdx.y];
   const int64_t s = ctrl->cursor;
   int64_t off = 0;
   for (int i = 0; i < d.n_sl; ++i) off |= ((s >> d.sbit[i]) & 1ll) << d.pos[i];
-  const float2* src = leaves + d.src_off + off;
-  float2* dst = bound + d.dst_off;
+  const E* src = leaves + d.src_off + off;
+  E* dst = bound + d.dst_off;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.n_elems;
        e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = src[e];
 }
 
-hipError_t launch_bind(const float2* leaves, float2* bound, const BindDesc* descs, int n_desc, int64_t max_elems,
-                       const Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,
+                       int64_t max_elems, const Ctrl* ctrl, hipStream_t s) {
   if (n_desc <= 0) return hipSuccess;
-  int64_t gx = std::min<int64_t>((max_elems + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_bind, dim3((unsigned)std::max<int64_t>(gx, 1), n_desc), dim3(256), 0, s, leaves, bound,
-                     descs, ctrl);
+  const int64_t gx = std::max<int64_t>(std::min<int64_t>((max_elems + 255) / 256, 1024), 1);
+  const dim3 g((unsigned)gx, n_desc);
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_bind<float2>, g, dim3(256), 0, s, (const float2*)leaves, (float2*)bound, descs, ctrl);
+  else
+    hipLaunchKernelGGL(k_bind<uint32_t>, g, dim3(256), 0, s, (const uint32_t*)leaves, (uint32_t*)bound, descs,
+                       ctrl);
   return hipGetLastError();
 }
 
@@ -87,12 +88,12 @@ __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 // a thread's loads are issued before any LDS store so they are in flight
 // together.  The per-element parts of the offsets that depend only on the
 // unrolled iteration are tabulated once in LDS.
-template <int TB>
-__global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restrict__ in, float2* __restrict__ out,
+template <int TB, typename E>
+__global__ __launch_bounds__(kPermThreads) void k_permute(const E* __restrict__ in, E* __restrict__ out,
                                                          const PermArgs a) {
   constexpr int NT = 1 << TB;
   constexpr int PER = NT / kPermThreads;
-  __shared__ float2 tile[NT + NT / 16];
+  __shared__ E tile[NT + NT / 16];
   __shared__ uint64_t hi_in[PER], hi_out[PER];
   __shared__ int hi_fe[PER];
   const int tid = threadIdx.x;
@@ -101,8 +102,8 @@ __global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restri
     hi_out[tid] = dep((uint64_t)tid * kPermThreads, a.out_tile);
     hi_fe[tid] = (int)dep((uint64_t)tid * kPermThreads, a.f2e);
   }
-  const float2* src = in + (int64_t)blockIdx.y * a.stride;
-  float2* dst = out + (int64_t)blockIdx.y * a.stride;
+  const E* src = in + (int64_t)blockIdx.y * a.stride;
+  E* dst = out + (int64_t)blockIdx.y * a.stride;
   const uint64_t e_t = dep((uint64_t)tid, a.in_tile);
   const uint64_t f_t = dep((uint64_t)tid, a.out_tile);
   const int fe_t = (int)dep((uint64_t)tid, a.f2e);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restri
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const uint64_t ib = dep((uint64_t)t, a.id_in) | e_t;
     const uint64_t ob = dep((uint64_t)t, a.id_out) | f_t;
-    float2 v[PER];
+    E v[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) v[i] = src[ib | hi_in[i]];
 #pragma unroll
@@ -125,18 +126,38 @@ __global__ __launch_bounds__(kPermThreads) void k_permute(const float2* __restri
 }
 
 // Tensors below 256 elements: one element per thread, direct gather.
-__global__ __launch_bounds__(256) void k_permute_small(const float2* __restrict__ in, float2* __restrict__ out,
+template <typename E>
+__global__ __launch_bounds__(256) void k_permute_small(const E* __restrict__ in, E* __restrict__ out,
                                                       const PermArgs a) {
   const int64_t n = (int64_t)1 << a.tbits;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const float2* src = in + (int64_t)blockIdx.y * a.stride;
-    float2* dst = out + (int64_t)blockIdx.y * a.stride;
-    dst[dep((uint64_t)e, a.out_tile)] = src[dep((uint64_t)e, a.f2e)];
+  const E* src = in + (int64_t)blockIdx.y * a.stride;
+  E* dst = out + (int64_t)blockIdx.y * a.stride;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) dst[dep((uint64_t)e, a.out_tile)] = src[dep((uint64_t)e, a.f2e)];
+}
+
+template <typename E>
+static void launch_perm_tb(int tb, dim3 g, const E* in, E* out, const PermArgs& A, hipStream_t s) {
+  switch (tb) {
+    case 8:
+      hipLaunchKernelGGL((k_permute<8, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 9:
+      hipLaunchKernelGGL((k_permute<9, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 10:
+      hipLaunchKernelGGL((k_permute<10, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    case 11:
+      hipLaunchKernelGGL((k_permute<11, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    default:
+      hipLaunchKernelGGL((k_permute<12, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
   }
 }
 
-hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int32_t* perm, int64_t batch,
-                              hipStream_t s) {
+hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, const int32_t* perm, int64_t batch,
+                          hipStream_t s) {
   // inverse map: input position p -> output position inv[p]
   std::vector<int> inv(rank, -1);
   for (int q = 0; q < rank; ++q) {
@@ -155,7 +176,12 @@ hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int
     A.tbits = rank;
     A.n_tiles = 1;
     if (!make_runs(po, &A.out_tile) || !make_runs(pi, &A.f2e)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_permute_small, dim3(1, (unsigned)batch), dim3(256), 0, s, in, out, A);
+    if (elem_bytes == 8)
+      hipLaunchKernelGGL(k_permute_small<float2>, dim3(1, (unsigned)batch), dim3(256), 0, s, (const float2*)in,
+                         (float2*)out, A);
+    else
+      hipLaunchKernelGGL(k_permute_small<uint32_t>, dim3(1, (unsigned)batch), dim3(256), 0, s,
+                         (const uint32_t*)in, (uint32_t*)out, A);
     return hipGetLastError();
   }
   // choose the tile: grow input-fast and output-fast bit sets alternately
@@ -197,310 +223,58 @@ hipError_t launch_permute_c64(const float2* in, float2* out, int rank, const int
   if (!make_runs(p1, &A.in_tile) || !make_runs(p2, &A.out_tile) || !make_runs(p3, &A.f2e) ||
       !make_runs(p4, &A.id_in) || !make_runs(p5, &A.id_out))
     return hipErrorInvalidValue;
+  if (A.tbits < 8 || A.tbits > kPermTileBits) return hipErrorInvalidValue;
   const int64_t grid = std::min<int64_t>(A.n_tiles, 16384);
   const dim3 g((unsigned)grid, (unsigned)batch);
-  switch (A.tbits) {
-    case 8:
-      hipLaunchKernelGGL(k_permute<8>, g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    case 9:
-      hipLaunchKernelGGL(k_permute<9>, g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    case 10:
-      hipLaunchKernelGGL(k_permute<10>, g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    case 11:
-      hipLaunchKernelGGL(k_permute<11>, g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    case 12:
-      hipLaunchKernelGGL(k_permute<12>, g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------- GEMM --
-// C[M][N] = sum_k A[M][K] B[N][K], complex64 in and out, FP32 accumulation on
-// v_mfma_f32_32x32x2_f32.  4M form: Cr += ArBr + (-Ai)Bi, Ci += ArBi + AiBr
-// (four real products).  3M form: T1 = ArBr, T2 = AiBi,
-// T3 = (Ar+Ai)(Br+Bi); Cr = T1 - T2, Ci = T3 - T1 - T2 (three products).
-// Workgroup tile 64x64, four waves of 32x32, K staged through LDS in steps of
-// 16 with re/im split into planar arrays.
-
-constexpr int GBM = 64, GBN = 64, GBK = 16;
-
-template <int FORM>
-__global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, const float2* __restrict__ B,
-                                              float2* __restrict__ C, int64_t M, int64_t N, int64_t K) {
-  __shared__ float As[2][GBK][GBM + 4];
-  __shared__ float Bs[2][GBK][GBN + 4];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t bm = (int64_t)blockIdx.x * GBM, bn = (int64_t)blockIdx.y * GBN;
-  const int64_t z = blockIdx.z;
-  A += z * M * K;
-  B += z * N * K;
-  C += z * M * N;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  floatx16 c0 = {}, c1 = {}, c2 = {};
-  const int lrow = tid >> 2, lk = (tid & 3) * 4;
-  const float2* Ap = A + (bm + lrow) * K + lk;
-  const float2* Bp = B + (bn + lrow) * K + lk;
-  for (int64_t k0 = 0; k0 < K; k0 += GBK) {
-    const float4 a01 = *reinterpret_cast<const float4*>(Ap + k0);
-    const float4 a23 = *reinterpret_cast<const float4*>(Ap + k0 + 2);
-    const float4 b01 = *reinterpret_cast<const float4*>(Bp + k0);
-    const float4 b23 = *reinterpret_cast<const float4*>(Bp + k0 + 2);
-    As[0][lk + 0][lrow] = a01.x;
-    As[1][lk + 0][lrow] = a01.y;
-    As[0][lk + 1][lrow] = a01.z;
-    As[1][lk + 1][lrow] = a01.w;
-    As[0][lk + 2][lrow] = a23.x;
-    As[1][lk + 2][lrow] = a23.y;
-    As[0][lk + 3][lrow] = a23.z;
-    As[1][lk + 3][lrow] = a23.w;
-    Bs[0][lk + 0][lrow] = b01.x;
-    Bs[1][lk + 0][lrow] = b01.y;
-    Bs[0][lk + 1][lrow] = b01.z;
-    Bs[1][lk + 1][lrow] = b01.w;
-    Bs[0][lk + 2][lrow] = b23.x;
-    Bs[1][lk + 2][lrow] = b23.y;
-    Bs[0][lk + 3][lrow] = b23.z;
-    Bs[1][lk + 3][lrow] = b23.w;
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GBK; kk += 2) {
-      const int kr = kk + (lane >> 5);
-      const float ar = As[0][kr][wm + (lane & 31)];
-      const float ai = As[1][kr][wm + (lane & 31)];
-      const float br = Bs[0][kr][wn + (lane & 31)];
-      const float bi = Bs[1][kr][wn + (lane & 31)];
-      if (FORM == TN_GEMM_3M) {
-        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, c1, 0, 0, 0);
-        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, c2, 0, 0, 0);
-      } else {
-        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c0, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, c1, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, c1, 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  const int j = lane & 31;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    float2 v;
-    if (FORM == TN_GEMM_3M) {
-      v.x = c0[r] - c1[r];
-      v.y = c2[r] - c0[r] - c1[r];
-    } else {
-      v.x = c0[r];
-      v.y = c1[r];
-    }
-    C[(bm + wm + i) * N + bn + wn + j] = v;
-  }
-}
-
-// 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32 MFMA
-// tiles), K staged through LDS 16 at a time; the next K tile is loaded into
-// registers while the current one is multiplied.  Planar LDS: re, im (and,
-// for 3M, re+im formed once per element when the tile is stored).  blockIdx.z
-// selects a batch entry or a split-K slab through the strides sA, sB, sC.
-template <int FORM>
-__global__ __launch_bounds__(256) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
-                                                 float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
-                                                 int64_t sA, int64_t sB, int64_t sC) {
-  constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
-  constexpr int BM = 128, BN = 128, BK = 16, LD = BM + 2;
-  __shared__ float As[P][BK][LD];
-  __shared__ float Bs[P][BK][LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t bm = (int64_t)blockIdx.x * BM, bn = (int64_t)blockIdx.y * BN;
-  const int64_t z = blockIdx.z;
-  A += z * sA;
-  B += z * sB;
-  C += z * sC;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  floatx16 acc[P][2][2];
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[p][i][j] = floatx16{};
-  const int lrow = tid >> 1, lk = (tid & 1) * 8;
-  const float2* Ap = A + (bm + lrow) * K + lk;
-  const float2* Bp = B + (bn + lrow) * K + lk;
-  float4 ra[4], rb[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    ra[j] = *reinterpret_cast<const float4*>(Ap + 2 * j);
-    rb[j] = *reinterpret_cast<const float4*>(Bp + 2 * j);
-  }
-  const int c = lane & 31, kh = lane >> 5;
-  for (int64_t k0 = 0; k0 < k_len; k0 += BK) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      As[0][lk + 2 * j][lrow] = ra[j].x;
-      As[1][lk + 2 * j][lrow] = ra[j].y;
-      As[0][lk + 2 * j + 1][lrow] = ra[j].z;
-      As[1][lk + 2 * j + 1][lrow] = ra[j].w;
-      Bs[0][lk + 2 * j][lrow] = rb[j].x;
-      Bs[1][lk + 2 * j][lrow] = rb[j].y;
-      Bs[0][lk + 2 * j + 1][lrow] = rb[j].z;
-      Bs[1][lk + 2 * j + 1][lrow] = rb[j].w;
-      if (P == 3) {
-        As[P - 1][lk + 2 * j][lrow] = ra[j].x + ra[j].y;
-        As[P - 1][lk + 2 * j + 1][lrow] = ra[j].z + ra[j].w;
-        Bs[P - 1][lk + 2 * j][lrow] = rb[j].x + rb[j].y;
-        Bs[P - 1][lk + 2 * j + 1][lrow] = rb[j].z + rb[j].w;
-      }
-    }
-    __syncthreads();
-    if (k0 + BK < k_len) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ra[j] = *reinterpret_cast<const float4*>(Ap + k0 + BK + 2 * j);
-        rb[j] = *reinterpret_cast<const float4*>(Bp + k0 + BK + 2 * j);
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      const int kr = kk + kh;
-      float a[P][2], b[P][2];
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          a[p][i] = As[p][kr][wm + 32 * i + c];
-          b[p][i] = Bs[p][kr][wn + 32 * i + c];
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (FORM == TN_GEMM_3M) {
-            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
-            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][i], b[1][j], acc[1][i][j], 0, 0, 0);
-            acc[P - 1][i][j] =
-                __builtin_amdgcn_mfma_f32_32x32x2f32(a[P - 1][i], b[P - 1][j], acc[P - 1][i][j], 0, 0, 0);
-          } else {
-            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
-            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][i], b[1][j], acc[0][i][j], 0, 0, 0);
-            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[1][j], acc[1][i][j], 0, 0, 0);
-            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][i], b[0][j], acc[1][i][j], 0, 0, 0);
-          }
-        }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int col = wn + 32 * j + c;
-        float2 v;
-        if (FORM == TN_GEMM_3M) {
-          v.x = acc[0][i][j][r] - acc[1][i][j][r];
-          v.y = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
-        } else {
-          v.x = acc[0][i][j][r];
-          v.y = acc[1][i][j][r];
-        }
-        C[(bm + row) * N + bn + col] = v;
-      }
-}
-
-// C[i] = sum over slabs s (in order) of W[s][i].
-__global__ __launch_bounds__(256) void k_splitk_sum(const float2* __restrict__ W, float2* __restrict__ C, int64_t n,
-                                                   int slabs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float r = 0.f, im = 0.f;
-    for (int sl = 0; sl < slabs; ++sl) {
-      const float2 v = W[(int64_t)sl * n + i];
-      r += v.x;
-      im += v.y;
-    }
-    C[i] = make_float2(r, im);
-  }
-}
-
-bool gemm_shape_ok(int64_t M, int64_t N, int64_t K) {
-  return M > 0 && N > 0 && K > 0 && M % GBM == 0 && N % GBN == 0 && K % GBK == 0;
-}
-
-hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
-                           int64_t batch, int form, hipStream_t s, float2* work, int splits) {
-  if (!gemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
-  if (batch == 0) return hipSuccess;
-  if (splits < 1) splits = 1;
-  const bool big = (M % 128 == 0) && (N % 128 == 0);
-  if (splits > 1) {
-    if (batch != 1 || !work || !big || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
-    const int64_t kl = K / splits;
-    dim3 grid((unsigned)(M / 128), (unsigned)(N / 128), (unsigned)splits);
-    if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N);
-    else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N);
-    const int64_t n = M * N;
-    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
-                       work, C, n, splits);
-    return hipGetLastError();
-  }
-  if (batch > 65535) return hipErrorInvalidValue;
-  if (big) {
-    dim3 grid((unsigned)(M / 128), (unsigned)(N / 128), (unsigned)batch);
-    if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N);
-    else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N);
-    return hipGetLastError();
-  }
-  dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)batch);
-  if (form == TN_GEMM_3M)
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+  if (elem_bytes == 8)
+    launch_perm_tb<float2>(A.tbits, g, (const float2*)in, (float2*)out, A, s);
   else
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+    launch_perm_tb<uint32_t>(A.tbits, g, (const uint32_t*)in, (uint32_t*)out, A, s);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- generic --
-// One output element per thread: C[(m<<nN)|n] = sum_k A[dep(m)|dep(k)] B[dep(n)|dep(k)].
+// One output element per thread: C[(m<<nN)|n] = sum_k A[dep(m)|dep(k)] B[dep(n)|dep(k)],
+// accumulated in FP32, multiplied by the op's output scale before storage.
 
-__global__ __launch_bounds__(256) void k_generic(const float2* __restrict__ A, const float2* __restrict__ B,
-                                                float2* __restrict__ C, const IndexOp op) {
+template <typename E>
+__global__ __launch_bounds__(256) void k_generic(const E* __restrict__ A, const E* __restrict__ B,
+                                                E* __restrict__ C, const IndexOp op, float* maxslot) {
   const int64_t nC = (int64_t)1 << (op.nM + op.nN);
   const int64_t nK = (int64_t)1 << op.nK;
   const uint64_t nmask = (1ull << op.nN) - 1ull;
+  float mx = 0.f;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nC; c += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t m = (uint64_t)c >> op.nN, n = (uint64_t)c & nmask;
     const uint64_t ab = dep(m, op.aM), bb = dep(n, op.bN);
     float re = 0.f, im = 0.f;
     for (int64_t k = 0; k < nK; ++k) {
-      const float2 x = A[ab | dep((uint64_t)k, op.aK)];
-      const float2 y = B[bb | dep((uint64_t)k, op.bK)];
+      const float2 x = to_f2(A[ab | dep((uint64_t)k, op.aK)]);
+      const float2 y = to_f2(B[bb | dep((uint64_t)k, op.bK)]);
       re = fmaf(x.x, y.x, re);
       re = fmaf(-x.y, y.y, re);
       im = fmaf(x.x, y.y, im);
       im = fmaf(x.y, y.x, im);
     }
-    C[c] = make_float2(re, im);
+    mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+    C[c] = from_f2<E>(re * op.out_scale, im * op.out_scale);
   }
+  record_max(maxslot, mx);
 }
 
-hipError_t launch_generic_c64(const float2* A, const float2* B, float2* C, const IndexOp& op, hipStream_t s) {
+hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
+                          hipStream_t s) {
   const int64_t nC = (int64_t)1 << (op.nM + op.nN);
-  int64_t grid = std::min<int64_t>((nC + 255) / 256, 16384);
-  hipLaunchKernelGGL(k_generic, dim3((unsigned)grid), dim3(256), 0, s, A, B, C, op);
+  const int64_t grid = std::min<int64_t>((nC + 255) / 256, 16384);
+  const dim3 g((unsigned)grid);
+  if (dtype == TN_DTYPE_F16S)
+    hipLaunchKernelGGL(k_generic<cf16>, g, dim3(256), 0, s, (const cf16*)A, (const cf16*)B, (cf16*)C, op, maxslot);
+  else if (dtype == TN_DTYPE_BF16S)
+    hipLaunchKernelGGL(k_generic<cbf16>, g, dim3(256), 0, s, (const cbf16*)A, (const cbf16*)B, (cbf16*)C, op,
+                       maxslot);
+  else
+    hipLaunchKernelGGL(k_generic<float2>, g, dim3(256), 0, s, (const float2*)A, (const float2*)B, (float2*)C, op,
+                       maxslot);
   return hipGetLastError();
 }
 
@@ -509,10 +283,10 @@ hipError_t launch_generic_c64(const float2* A, const float2* B, float2* C, const
 // fixed grid; each thread accumulates all outputs over its k's (consecutive
 // threads take consecutive k, so the gathers are coalesced wherever the low
 // K bits are the operands' low bits), the block reduces in LDS, and one
-// block sums the per-block partials in a fixed order.
+// block sums the FP32 per-block partials in a fixed order.
 
-template <int NOUT>
-__global__ __launch_bounds__(256) void k_splitk_part(const float2* __restrict__ A, const float2* __restrict__ B,
+template <int NOUT, typename E>
+__global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, const E* __restrict__ B,
                                                     float2* __restrict__ part, const IndexOp op) {
   __shared__ uint64_t am[NOUT], bn[NOUT];
   __shared__ float red[2][256];
@@ -533,8 +307,8 @@ __global__ __launch_bounds__(256) void k_splitk_part(const float2* __restrict__ 
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
       if (o < nout) {
-        const float2 x = A[am[o] | ak];
-        const float2 y = B[bn[o] | bk];
+        const float2 x = to_f2(A[am[o] | ak]);
+        const float2 y = to_f2(B[bn[o] | bk]);
         acc_r[o] = fmaf(x.x, y.x, acc_r[o]);
         acc_r[o] = fmaf(-x.y, y.y, acc_r[o]);
         acc_i[o] = fmaf(x.x, y.y, acc_i[o]);
@@ -561,10 +335,12 @@ __global__ __launch_bounds__(256) void k_splitk_part(const float2* __restrict__ 
   }
 }
 
+template <typename E>
 __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__ part, int nblk, int nout,
-                                                     float2* __restrict__ C) {
+                                                     E* __restrict__ C, float out_scale, float* maxslot) {
   __shared__ float red[2][256];
   const int tid = threadIdx.x;
+  float mx = 0.f;
   for (int o = 0; o < nout; ++o) {
     float r = 0.f, i = 0.f;
     for (int g = tid; g < nblk; g += 256) {
@@ -582,51 +358,94 @@ __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__
       }
       __syncthreads();
     }
-    if (tid == 0) C[o] = make_float2(red[0][0], red[1][0]);
+    if (tid == 0) {
+      mx = fmaxf(mx, fmaxf(fabsf(red[0][0]), fabsf(red[1][0])));
+      C[o] = from_f2<E>(red[0][0] * out_scale, red[1][0] * out_scale);
+    }
     __syncthreads();
   }
+  record_max(maxslot, mx);
 }
 
 int64_t splitk_blocks(const IndexOp& op) { return splitk_grid(op.nK); }
 
-hipError_t launch_splitk_c64(const float2* A, const float2* B, float2* C, float2* part, const IndexOp& op,
-                             hipStream_t s) {
+template <typename E>
+static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const IndexOp& op, float* maxslot,
+                            hipStream_t s) {
   const int nout = 1 << (op.nM + op.nN);
-  if (nout > 64) return hipErrorInvalidValue;
   const int64_t g = splitk_blocks(op);
   if (nout <= 4)
-    hipLaunchKernelGGL(k_splitk_part<4>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+    hipLaunchKernelGGL((k_splitk_part<4, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
   else if (nout <= 16)
-    hipLaunchKernelGGL(k_splitk_part<16>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+    hipLaunchKernelGGL((k_splitk_part<16, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
   else
-    hipLaunchKernelGGL(k_splitk_part<64>, dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
-  hipLaunchKernelGGL(k_splitk_final, dim3(1), dim3(256), 0, s, part, (int)g, nout, C);
+    hipLaunchKernelGGL((k_splitk_part<64, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+  hipLaunchKernelGGL(k_splitk_final<E>, dim3(1), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot);
+}
+
+hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
+                         float* maxslot, hipStream_t s) {
+  const int nout = 1 << (op.nM + op.nN);
+  if (nout > 64) return hipErrorInvalidValue;
+  if (dtype == TN_DTYPE_F16S)
+    launch_splitk_t<cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, part, op, maxslot, s);
+  else if (dtype == TN_DTYPE_BF16S)
+    launch_splitk_t<cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, part, op, maxslot, s);
+  else
+    launch_splitk_t<float2>((const float2*)A, (const float2*)B, (float2*)C, part, op, maxslot, s);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ accumulate --
-// amp[y] += (double) root[dep(y)] for the current slice; raises the
-// non-finite flag; advances the slice cursor.
+// amp[y] += root[dep(y)] * 2^e_root in FP64 for the current slice; raises the
+// non-finite flag; evaluates and clears the per-op magnitude records of
+// scaled storage (overflow: a stored magnitude reached the format's maximum;
+// underflow: an op's largest stored magnitude fell below `under`); advances
+// the slice cursor.
 
-__global__ __launch_bounds__(256) void k_accum(const float2* __restrict__ root, const Runs y2root, int n_open,
-                                              Ctrl* ctrl) {
+template <typename E>
+__global__ __launch_bounds__(256) void k_accum(const E* __restrict__ root, const Runs y2root, int n_open,
+                                              double root_scale, Ctrl* ctrl, float* maxslots,
+                                              const float* __restrict__ out_scales, int n_slots, float over,
+                                              float under) {
   double* amp = ctrl->amp;
   const int64_t n = (int64_t)1 << n_open;
   bool bad = false;
   for (int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; y < n; y += (int64_t)gridDim.x * blockDim.x) {
-    const float2 v = root[dep((uint64_t)y, y2root)];
+    const float2 v = to_f2(root[dep((uint64_t)y, y2root)]);
     bad |= !(isfinite(v.x) && isfinite(v.y));
-    amp[2 * y] += (double)v.x;
-    amp[2 * y + 1] += (double)v.y;
+    amp[2 * y] += (double)v.x * root_scale;
+    amp[2 * y + 1] += (double)v.y * root_scale;
   }
   if (bad) atomicOr(&ctrl->flags, (unsigned)TN_FLAG_NONFINITE);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->cursor += 1;
+  if (blockIdx.x == 0) {
+    unsigned f = 0;
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+      const float m = maxslots[i] * out_scales[i];
+      if (!(m < over)) f |= TN_FLAG_OVERFLOW;
+      if (m < under) f |= TN_FLAG_UNDERFLOW;
+      maxslots[i] = 0.f;
+    }
+    if (f) atomicOr(&ctrl->flags, f);
+    if (threadIdx.x == 0) ctrl->cursor += 1;
+  }
 }
 
-hipError_t launch_accum(const float2* root, const AccumDesc& d, Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,
+                        const float* out_scales, int n_slots, hipStream_t s) {
   const int64_t n = (int64_t)1 << d.n_open;
-  int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_accum, dim3((unsigned)grid), dim3(256), 0, s, root, d.y2root, d.n_open, ctrl);
+  const int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
+  const dim3 g((unsigned)grid);
+  const float under = 0.25f;
+  if (dtype == TN_DTYPE_F16S)
+    hipLaunchKernelGGL(k_accum<cf16>, g, dim3(256), 0, s, (const cf16*)root, d.y2root, d.n_open, d.root_scale, ctrl,
+                       maxslots, out_scales, n_slots, 65504.f, under);
+  else if (dtype == TN_DTYPE_BF16S)
+    hipLaunchKernelGGL(k_accum<cbf16>, g, dim3(256), 0, s, (const cbf16*)root, d.y2root, d.n_open, d.root_scale,
+                       ctrl, maxslots, out_scales, n_slots, 3.0e38f, under);
+  else
+    hipLaunchKernelGGL(k_accum<float2>, g, dim3(256), 0, s, (const float2*)root, d.y2root, d.n_open, d.root_scale,
+                       ctrl, maxslots, out_scales, 0, 3.0e38f, 0.f);
   return hipGetLastError();
 }
 
@@ -725,7 +544,7 @@ __global__ __launch_bounds__(256) void k_hist(const double* __restrict__ amp, in
 
 hipError_t launch_hist(const double* amp, int64_t n, double scale, double xmax, int n_bins,
                        unsigned long long* counts, hipStream_t s) {
-  int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
+  const int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hist, dim3((unsigned)grid), dim3(256), 0, s, amp, n, scale, xmax, n_bins, counts);
   return hipGetLastError();

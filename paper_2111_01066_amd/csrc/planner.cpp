@@ -226,9 +226,12 @@ static int build_network(PlanCore& P, std::vector<HostTensor>& leaves, std::stri
   return TN_OK;
 }
 
+static int elem_bytes_plan(const PlanCore& P) { return P.opts.dtype == TN_DTYPE_C64 ? 8 : 4; }
+
 static void add_stats_step(PlanCore& P, int nM, int nN, int nK, int ra, int rb, int rc) {
+  const double eb = elem_bytes_plan(P);
   P.stats.flops_per_slice += 8.0 * std::ldexp(1.0, nM + nN + nK);
-  P.stats.bytes_per_slice += 8.0 * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rc));
+  P.stats.bytes_per_slice += eb * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rc));
   if (nK < 64) P.stats.k_hist[nK]++;
 }
 
@@ -408,6 +411,7 @@ int build_plan(PlanCore& P, std::string& err) {
       where[d.ssa] = TRef{kLeaves, d.stored_off};
   }
   P.ops.clear();
+  P.n_slots = 0;
   std::vector<Buf> bufs;
   std::vector<int> buf_of_ssa(L + S, -1);
   struct Pending {
@@ -459,7 +463,10 @@ int build_plan(PlanCore& P, std::string& err) {
       return where[ssa];
     };
 
-    const bool dense = nM >= 6 && nN >= 6 && nK >= 4;
+    const bool half = P.opts.dtype != TN_DTYPE_C64;
+    const double eb = elem_bytes_plan(P);
+    const int64_t f2 = 8 / (int64_t)eb;  // plan elements per float2 workspace entry
+    const bool dense = half ? (nM >= 7 && nN >= 7 && nK >= 4) : (nM >= 6 && nN >= 6 && nK >= 4);
     if (dense) {
       // K order: keep whichever operand already has K as its lowest block
       auto k_low_block = [&](const std::vector<int>& Lx2, std::vector<int>& kord) {
@@ -497,7 +504,7 @@ int build_plan(PlanCore& P, std::string& err) {
         int tbi = (int)bufs.size();
         bufs.push_back(tb);
         fix.push_back({opi, 2, tbi});
-        op.bytes = 16.0 * std::ldexp(1.0, r);
+        op.bytes = 2.0 * eb * std::ldexp(1.0, r);
         P.ops.push_back(op);
         P.stats.n_permute++;
         if (side)
@@ -511,9 +518,11 @@ int build_plan(PlanCore& P, std::string& err) {
       g.gemm.M = (int64_t)1 << nM;
       g.gemm.N = (int64_t)1 << nN;
       g.gemm.K = (int64_t)1 << nK;
-      // auto: the 3M form (three real products per complex product) is the
-      // faster one on every compute-bound shape measured; 4M on request
-      g.gemm.form = P.opts.gemm_form == TN_GEMM_4M ? TN_GEMM_4M : TN_GEMM_3M;
+      // auto: on FP32 matrix cores the 3M form (three real products per
+      // complex product) is the faster one on every compute-bound shape
+      // measured; on FP16/BF16 cores 4M is (3M's third operand plane makes
+      // those kernels bound by LDS bandwidth)
+      g.gemm.form = P.opts.gemm_form != TN_GEMM_AUTO ? P.opts.gemm_form : (half ? TN_GEMM_4M : TN_GEMM_3M);
       int gi = (int)P.ops.size();
       // split K when the output has too few 128x128 tiles to fill the chip
       if (nM >= 7 && nN >= 7) {
@@ -524,7 +533,7 @@ int build_plan(PlanCore& P, std::string& err) {
           sp *= 2;
         if (sp > 1) {
           g.gemm.split_k = sp;
-          Buf wb{(int64_t)sp << (nM + nN), dstep, dstep, -1, (int)bufs.size()};
+          Buf wb{((int64_t)sp << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
           fix.push_back({gi, 3, (int)bufs.size()});
           bufs.push_back(wb);
         }
@@ -541,7 +550,11 @@ int build_plan(PlanCore& P, std::string& err) {
       g.b = bref;
       fix.push_back({gi, 2, cbuf});
       g.flops = 8.0 * std::ldexp(1.0, nM + nN + nK);
-      g.bytes = 8.0 * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rcn));
+      g.bytes = eb * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rcn));
+      g.ssa_a = ia;
+      g.ssa_b = ib;
+      g.ssa_c = L + t;
+      if (half) g.max_slot = P.n_slots++;
       P.ops.push_back(g);
       P.stats.n_dense++;
     } else {
@@ -575,12 +588,16 @@ int build_plan(PlanCore& P, std::string& err) {
       g.b = operand_ref(ib, gi, 1);
       fix.push_back({gi, 2, cbuf});
       if (splitk) {
-        Buf wb{splitk_grid(nK) << (nM + nN), dstep, dstep, -1, (int)bufs.size()};
+        Buf wb{(splitk_grid(nK) << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
         fix.push_back({gi, 3, (int)bufs.size()});
         bufs.push_back(wb);
       }
       g.flops = 8.0 * std::ldexp(1.0, nM + nN + nK);
-      g.bytes = 8.0 * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rcn));
+      g.bytes = eb * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb) + std::ldexp(1.0, rcn));
+      g.ssa_a = ia;
+      g.ssa_b = ib;
+      g.ssa_c = L + t;
+      if (half) g.max_slot = P.n_slots++;
       P.ops.push_back(g);
       P.stats.n_generic++;
     }
@@ -612,6 +629,7 @@ int build_plan(PlanCore& P, std::string& err) {
       err = "output map too fragmented";
       return TN_E_UNSUPPORTED;
     }
+    P.accum.root_ssa = root;
     if (P.root_is_leaf)
       P.accum.root = where[root];
     else
@@ -631,8 +649,8 @@ int build_plan(PlanCore& P, std::string& err) {
   st.n_kernels = (int)P.ops.size() + 1 + (P.binds.empty() ? 0 : 1);
   st.max_log2 = max_log2;
   st.n_open = (int)P.open_wires.size();
-  st.arena_bytes = P.arena_elems * 8;
-  st.leaf_bytes = (P.leaves_elems + P.bound_elems) * 8;
+  st.arena_bytes = P.arena_elems * elem_bytes_plan(P);
+  st.leaf_bytes = (P.leaves_elems + P.bound_elems) * elem_bytes_plan(P);
   // JSON
   std::ostringstream js;
   js << "{\"n_leaves\":" << L << ",\"n_wires\":" << P.n_wires << ",\"arena_elems\":" << P.arena_elems
@@ -673,7 +691,7 @@ int build_plan(PlanCore& P, std::string& err) {
       js << "]";
     } else if (op.kind == kOpGemm) {
       js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
-         << ",\"split_k\":" << op.gemm.split_k << ",\"w\":";
+         << ",\"split_k\":" << op.gemm.split_k << ",\"s_out\":" << op.s_out << ",\"w\":";
       json_ref(js, op.w);
     } else {
       js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
@@ -684,7 +702,7 @@ int build_plan(PlanCore& P, std::string& err) {
       json_runs(js, op.idx.bN);
       js << ",\"bK\":";
       json_runs(js, op.idx.bK);
-      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK << ",\"w\":";
+      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK << ",\"s_out\":" << op.s_out << ",\"w\":";
       json_ref(js, op.w);
     }
     js << "}";
@@ -697,6 +715,31 @@ int build_plan(PlanCore& P, std::string& err) {
   P.json = js.str();
   (void)n;
   return TN_OK;
+}
+
+void leaf_exponents(PlanCore& P) {
+  for (DevLeaf& d : P.dev_leaves) {
+    double mx = 0;
+    for (const cd& v : d.data) mx = std::max({mx, std::fabs(v.real()), std::fabs(v.imag())});
+    d.e = mx > 0 ? (int)std::ceil(std::log2(mx)) - kTargetLog2 : 0;
+  }
+}
+
+void set_output_shift(Op& op, float max_acc) {
+  int s = 0;
+  if (max_acc > 0 && std::isfinite(max_acc)) s = (int)std::ceil(std::log2((double)max_acc)) - kTargetLog2;
+  op.s_out = s;
+  const float sc = (float)std::ldexp(1.0, -s);
+  op.gemm.out_scale = sc;
+  op.idx.out_scale = sc;
+}
+
+void propagate_exponents(PlanCore& P) {
+  std::map<int, int> e;
+  for (const DevLeaf& d : P.dev_leaves) e[d.ssa] = P.opts.dtype == TN_DTYPE_C64 ? 0 : d.e;
+  for (const Op& op : P.ops)
+    if (op.ssa_c >= 0) e[op.ssa_c] = e[op.ssa_a] + e[op.ssa_b] + op.s_out;
+  P.accum.root_scale = std::ldexp(1.0, e.count(P.accum.root_ssa) ? e[P.accum.root_ssa] : 0);
 }
 
 int refold_leaves(PlanCore& P, std::string& err) {

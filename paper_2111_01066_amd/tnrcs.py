@@ -76,7 +76,9 @@ _lib.tn_plan_set_output_bits.argtypes = [c_void_p, POINTER(c_uint8)]
 _lib.tn_plan_destroy.argtypes = [c_void_p]
 _lib.tn_plan_profile.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, POINTER(ctypes.c_float), c_int32,
                                  POINTER(c_int32)]
-_lib.tn_permute_c64.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32), c_int64, c_void_p]
+_lib.tn_permute.argtypes = [c_void_p, c_void_p, c_int32, c_int32, POINTER(c_int32), c_int64, c_void_p]
+_lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
+                               ctypes.c_float, c_void_p, c_int32, c_void_p, c_void_p]
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                               c_void_p, c_int32, c_void_p]
 _lib.tn_amp_norm2.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
@@ -85,7 +87,7 @@ _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_v
 
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error",
-            "tn_permute_c64", "tn_cgemm_c64", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
+            "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
 
 
 def _check(rc: int):
@@ -255,9 +257,9 @@ def tn_last_error() -> str:
     return _lib.tn_last_error().decode(errors="replace")
 
 
-def tn_permute_c64(inp, out, perm: Sequence[int], batch: int = 1, stream=None):
-    _check(_lib.tn_permute_c64(c_void_p(_ptr(inp)), c_void_p(_ptr(out)), len(perm), _i32(perm), int(batch),
-                               c_void_p(_stream(stream))))
+def tn_permute(inp, out, perm: Sequence[int], batch: int = 1, elem_bytes: int = 8, stream=None):
+    _check(_lib.tn_permute(c_void_p(_ptr(inp)), c_void_p(_ptr(out)), int(elem_bytes), len(perm), _i32(perm),
+                           int(batch), c_void_p(_stream(stream))))
 
 
 def tn_cgemm_c64(A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4m", work=None, splits: int = 1,
@@ -265,6 +267,14 @@ def tn_cgemm_c64(A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4
     _check(_lib.tn_cgemm_c64(c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(M), int(N), int(K),
                              int(batch), GEMM_FORMS[form], c_void_p(_ptr(work) if work is not None else None),
                              int(splits), c_void_p(_stream(stream))))
+
+
+def tn_cgemm_half(dtype: str, A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4m",
+                  out_scale: float = 1.0, work=None, splits: int = 1, max_out=None, stream=None):
+    _check(_lib.tn_cgemm_half(DTYPES[dtype], c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(M), int(N),
+                              int(K), int(batch), GEMM_FORMS[form], float(out_scale),
+                              c_void_p(_ptr(work) if work is not None else None), int(splits),
+                              c_void_p(_ptr(max_out) if max_out is not None else None), c_void_p(_stream(stream))))
 
 
 def tn_amp_norm2(amp, n: int, out, stream=None):

@@ -127,3 +127,28 @@ def test_tiny_networks():
     plan = tnrcs.Plan(c, greedy_order(ns, 0), [], open_q, None)
     np.testing.assert_allclose(_amps(plan, 4, [(0, 1)]), oracle.statevector(c).reshape(-1), atol=1e-6)
     plan.close()
+
+
+TOL_HALF = {"f16s": 1e-2, "bf16s": 6e-2}
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+@pytest.mark.parametrize("d,open_q,S", [(8, list(range(20)), 40), (12, [], 22), (10, [0, 1, 2, 3, 4, 5], 20),
+                                        (12, list(range(20)), 24)])
+def test_scaled_half_precision_vs_oracle(dtype, d, open_q, S):
+    c = make_rqc(4, 5, d, seed=5)
+    bits = random_bitstrings(20, 1, seed=8)[0]
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, S)
+    print(f"{dtype} 4x5 d={d} open={len(open_q)} k={len(sliced)}", flush=True)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype)
+    info = plan.info()
+    amp = _amps(plan, len(open_q), [(0, info["n_slices"])])
+    flags = plan.status()
+    ref = oracle.amplitudes_sv(c, open_q, bits)
+    err = oracle.relative_error_norm(amp, ref)
+    print(f"  relative error {err:.3e}, flags {flags}", flush=True)
+    assert flags & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
+    assert err < TOL_HALF[dtype], err
+    plan.close()

@@ -37,7 +37,7 @@ def test_permute_bit_exact(rank):
         xin = torch.from_numpy(x).to(DEV)
         out = torch.empty_like(xin)
         print(f"permute rank={rank} trial={trial}", flush=True)
-        tnrcs.tn_permute_c64(xin, out, perm, batch=2)
+        tnrcs.tn_permute(xin, out, perm, batch=2)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
 
@@ -45,13 +45,13 @@ def test_permute_bit_exact(rank):
 def test_permute_rejects_bad_perm():
     x = torch.zeros(8, dtype=torch.complex64, device=DEV)
     with pytest.raises(tnrcs.TnError):
-        tnrcs.tn_permute_c64(x, torch.empty_like(x), [0, 0, 1])
+        tnrcs.tn_permute(x, torch.empty_like(x), [0, 0, 1])
 
 
 @pytest.mark.parametrize("form", ["4m", "3m"])
 @pytest.mark.parametrize("M,N,K,batch", [(64, 64, 16, 1), (128, 64, 48, 2), (256, 192, 512, 1),
                                          (64, 512, 4096, 1), (128, 128, 16, 1), (256, 384, 1024, 2),
-                                         (512, 256, 4096, 1)])
+                                         (512, 256, 4096, 1), (1280, 256, 256, 1), (384, 1152, 64, 1)])
 def test_cgemm_matches_fp64(form, M, N, K, batch):
     rng = np.random.default_rng(M + N + K)
     A = _rand_c64(rng, batch, M, K)
@@ -116,3 +116,58 @@ def test_reductions():
     x = scale * np.abs(a) ** 2
     ref = np.minimum((x / 8.0 * 16).astype(np.int64), 15)
     np.testing.assert_array_equal(counts.cpu().numpy(), np.bincount(ref, minlength=16))
+
+
+def _to_pairs(z, dtype):
+    """complex array -> torch tensor of (re, im) 16-bit pairs (last dim 2)."""
+    t = torch.stack([torch.from_numpy(np.ascontiguousarray(z.real)), torch.from_numpy(np.ascontiguousarray(z.imag))],
+                    dim=-1)
+    return t.to(torch.float16 if dtype == "f16s" else torch.bfloat16).contiguous()
+
+
+def _from_pairs(t):
+    x = t.float().cpu().numpy().astype(np.float64)
+    return x[..., 0] + 1j * x[..., 1]
+
+
+@pytest.mark.parametrize("rank", [3, 9, 14, 21])
+def test_permute_4byte_bit_exact(rank):
+    rng = np.random.default_rng(100 + rank)
+    perm = rng.permutation(rank).tolist()
+    x = rng.integers(0, 2**31, size=(3, 1 << rank), dtype=np.int64).astype(np.int32)
+    xin = torch.from_numpy(x).to(DEV)
+    out = torch.empty_like(xin)
+    print(f"permute 4-byte rank={rank}", flush=True)
+    tnrcs.tn_permute(xin, out, perm, batch=3, elem_bytes=4)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+@pytest.mark.parametrize("form", ["4m", "3m"])
+@pytest.mark.parametrize("M,N,K,batch,splits", [(128, 128, 16, 1, 1), (256, 384, 1024, 2, 1),
+                                                (128, 256, 4096, 1, 8), (512, 128, 96, 1, 1), (64, 192, 32, 1, 1),
+                                                (1280, 256, 128, 1, 1), (192, 320, 1024, 1, 4)])
+def test_cgemm_half(dtype, form, M, N, K, batch, splits):
+    rng = np.random.default_rng(M + 3 * N + K)
+    A = rng.standard_normal((batch, M, K)) + 1j * rng.standard_normal((batch, M, K))
+    B = rng.standard_normal((batch, N, K)) + 1j * rng.standard_normal((batch, N, K))
+    dA, dB = _to_pairs(A, dtype).to(DEV), _to_pairs(B, dtype).to(DEV)
+    Aq, Bq = _from_pairs(dA), _from_pairs(dB)  # the rounded inputs
+    ref = np.einsum("bmk,bnk->bmn", Aq, Bq)
+    scale = 2.0 ** -int(np.ceil(np.log2(np.abs(ref).max())) - 12)
+    dC = torch.empty((batch, M, N, 2), dtype=dA.dtype, device=DEV)
+    mx = torch.zeros(1, dtype=torch.float32, device=DEV)
+    work = torch.empty((splits, M, N), dtype=torch.complex64, device=DEV) if splits > 1 else None
+    print(f"cgemm_half {dtype} {form} M={M} N={N} K={K} batch={batch} splits={splits}", flush=True)
+    tnrcs.tn_cgemm_half(dtype, dA, dB, dC, M, N, K, batch, form, out_scale=scale, work=work, splits=splits,
+                        max_out=mx)
+    torch.cuda.synchronize()
+    C = _from_pairs(dC) / scale
+    err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    u = 2.0 ** -11 if dtype == "f16s" else 2.0 ** -8
+    # output rounding (and, for 3M, the rounded re+im operand sums)
+    assert err < (2 if form == "4m" else 4) * u + 1e-6 * np.sqrt(K), err
+    # the record is the largest |component| of the FP32 result before rounding
+    comp_max = max(np.abs(C.real).max(), np.abs(C.imag).max())
+    assert abs(mx.item() - comp_max) <= 2 * u * comp_max

@@ -55,14 +55,15 @@ def test_dryrun_plan_matches_oracle(rows, cols, d, seed, open_q, finder, S, fold
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["c64", "f16s"])
 @pytest.mark.parametrize("d,open_q,S", [(12, [], 22), (10, [0, 1, 2, 3, 4, 5], 20)])
-def test_dryrun_dense_steps_present(d, open_q, S):
+def test_dryrun_dense_steps_present(d, open_q, S, dtype):
     c = make_rqc(4, 5, d, 5)
     bits = random_bitstrings(20, 1, seed=8)[0]
     ns = network_structure(c, open_q)
     pairs = bisection_order(ns, seed=0)
     sliced = slice_to_fit(ns, pairs, S)
-    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True, dtype=dtype)
     info = plan.info()
     assert info["n_dense"] > 0
     amp = _run_plan(plan, info["n_slices"], len(open_q))
