@@ -183,6 +183,26 @@ int tn_plan_destroy(tn_plan_t p);
 
 const char* tn_last_error(void);
 
+/* ---- one pairwise contraction (Supplement Eq. (matmul)) ---- */
+
+/* Plans C = sum over shared labels of A * B for caller tensors whose indices
+ * carry integer labels (0..4095, most significant first; every dimension 2):
+ * labels shared by A and B are contracted, and C's labels must be exactly
+ * the unshared ones, in the caller's order.  The planner picks the same
+ * kernels as for a network step (permute + MFMA GEMM, the skewed kernel,
+ * or a gathered contraction) and adds a final permute when its natural
+ * output order differs.  opts as for tn_plan (dtype, gemm_form, device;
+ * host folding and graphs are not used).  Release with tn_plan_destroy. */
+int tn_pair_plan(int32_t rank_a, const int32_t* labels_a, int32_t rank_b, const int32_t* labels_b, int32_t rank_c,
+                 const int32_t* labels_c, const tn_plan_opts* opts, tn_plan_t* out);
+
+/* Runs the pairwise plan on `batch` independent (A, B, C) triples stored
+ * consecutively (strides 2^rank_a, 2^rank_b, 2^rank_c elements of the plan's
+ * dtype; device memory, C must not overlap A or B), asynchronously on
+ * `stream`.  out_scale: for F16S/BF16S the FP32 product is multiplied by it
+ * before rounding (it must be 1 for complex64). */
+int tn_pair_run(tn_plan_t p, const void* A, const void* B, void* C, int64_t batch, float out_scale, void* stream);
+
 /* ---- standalone kernels of the hot path (same kernels the plans run) ---- */
 
 /* Binary-index tensor permutation (the index permutation of Supplement

@@ -127,3 +127,26 @@ def contract_sliced(leaves, pairs, open_wires, sliced: Sequence[int] = (),
         v = contract_slice(leaves, pairs, open_wires, sliced, s)
         total = v if total is None else total + v
     return total
+
+
+def contract_entry(sub_a: np.ndarray, shared_a, sub_b: np.ndarray, shared_b) -> complex:
+    """One output entry of Eq. (matmul): with every free index of A and B
+    fixed, the sum over the shared indices of A * B.  sub_a / sub_b hold the
+    remaining (shared) axes, labelled by shared_a / shared_b (the same labels,
+    possibly in different orders)."""
+    sb = np.transpose(sub_b, [list(shared_b).index(l) for l in shared_a]) if len(shared_a) else sub_b
+    return complex(np.sum(sub_a * sb))
+
+
+def contract_entries(a: np.ndarray, la, b: np.ndarray, lb, lc, coords) -> np.ndarray:
+    """Entries C[coords[i]] of C = sum over shared labels of A * B, entry by
+    entry (coords: output index values, one column per label of lc)."""
+    shared_a = [l for l in la if l in lb]
+    shared_b = [l for l in lb if l in la]
+    out = np.empty(len(coords), dtype=np.complex128)
+    for i, c in enumerate(coords):
+        fix = dict(zip(lc, (int(x) for x in c)))
+        sa = a[tuple(fix[l] if l in fix else slice(None) for l in la)]
+        sb = b[tuple(fix[l] if l in fix else slice(None) for l in lb)]
+        out[i] = contract_entry(sa, shared_a, sb, shared_b)
+    return out

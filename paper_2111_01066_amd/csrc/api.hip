@@ -80,10 +80,33 @@ struct tn_plan_s {
   hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
   bool ran = false;
+  // pairwise mode: caller buffers of the current run
+  const char* ext_a = nullptr;
+  const char* ext_b = nullptr;
+  char* ext_c = nullptr;
 };
 
 static char* resolve(const tn_plan_s* p, const TRef& r) {
-  char* base = r.region == kLeaves ? p->d_leaves : (r.region == kBound ? p->d_bound : p->d_arena);
+  char* base;
+  switch (r.region) {
+    case kLeaves:
+      base = p->d_leaves;
+      break;
+    case kBound:
+      base = p->d_bound;
+      break;
+    case kExtA:
+      base = const_cast<char*>(p->ext_a);
+      break;
+    case kExtB:
+      base = const_cast<char*>(p->ext_b);
+      break;
+    case kExtC:
+      base = p->ext_c;
+      break;
+    default:
+      base = p->d_arena;
+  }
   return base + r.off * (int64_t)p->eb;
 }
 
@@ -151,6 +174,9 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
       break;
     case kOpSplitK:
       HIP_TRY(launch_splitk(dt, a, b, c, w, op.idx, slot, s), "split-K kernel");
+      break;
+    case kOpSkinny:
+      HIP_TRY(launch_skinny(dt, a, b, c, op.idx, slot, s), "skewed contraction kernel");
       break;
     default:
       HIP_TRY(launch_generic(dt, a, b, c, op.idx, slot, s), "contraction kernel");
@@ -220,6 +246,7 @@ static int calibrate(tn_plan_s* p) {
   }
   HIP_TRY(hipDeviceSynchronize(), "calibration synchronize");
   propagate_exponents(P);
+  make_json(P);
   return upload_scales(p);
 }
 
@@ -366,8 +393,88 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   return TN_OK;
 }
 
+int tn_pair_plan(int32_t rank_a, const int32_t* labels_a, int32_t rank_b, const int32_t* labels_b, int32_t rank_c,
+                 const int32_t* labels_c, const tn_plan_opts* opts, tn_plan_t* out) {
+  if (!out) return fail(TN_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40 ||
+      (rank_a && !labels_a) || (rank_b && !labels_b) || (rank_c && !labels_c))
+    return fail(TN_E_ARG, "bad label list");
+  tn_plan_opts o;
+  if (opts)
+    o = *opts;
+  else
+    tn_plan_opts_default(&o);
+  if (o.dtype != TN_DTYPE_C64 && o.dtype != TN_DTYPE_F16S && o.dtype != TN_DTYPE_BF16S)
+    return fail(TN_E_ARG, "unknown dtype");
+  tn_plan_s* p = new (std::nothrow) tn_plan_s();
+  if (!p) return fail(TN_E_MEM, "host allocation failed");
+  PlanCore& P = p->core;
+  P.pair_a.assign(labels_a, labels_a + rank_a);
+  P.pair_b.assign(labels_b, labels_b + rank_b);
+  P.pair_out.assign(labels_c, labels_c + rank_c);
+  P.opts = o;
+  std::string err;
+  int rc = build_pair_plan(P, err);
+  if (rc) {
+    delete p;
+    return fail(rc, err);
+  }
+  p->device = o.device;
+  p->eb = elem_bytes_of(o.dtype);
+  if (o.dry_run) {
+    *out = p;
+    return TN_OK;
+  }
+  auto bail = [&](int code) {
+    release(p);
+    delete p;
+    return code;
+  };
+  hipError_t e = hipSetDevice(o.device);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
+  if ((e = hipMalloc((void**)&p->d_arena, (size_t)std::max<int64_t>(P.arena_elems * p->eb, 256))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_maxslots, (size_t)std::max(P.n_slots, 1) * 4)) != hipSuccess)
+    return bail(hip_fail(e, "alloc pair workspace"));
+  std::vector<float> zero(std::max(P.n_slots, 1), 0.f);
+  if ((e = hipMemcpy(p->d_maxslots, zero.data(), zero.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(hip_fail(e, "clear records"));
+  *out = p;
+  return TN_OK;
+}
+
+int tn_pair_run(tn_plan_t p, const void* A, const void* B, void* C, int64_t batch, float out_scale, void* stream) {
+  if (!p || !A || !B || !C) return fail(TN_E_ARG, "NULL argument");
+  if (!p->core.pair_mode) return fail(TN_E_ARG, "not a pairwise plan");
+  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
+  if (batch < 0) return fail(TN_E_ARG, "batch < 0");
+  if (p->core.opts.dtype == TN_DTYPE_C64 && out_scale != 1.f) return fail(TN_E_ARG, "out_scale must be 1 for complex64");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  PlanCore& P = p->core;
+  for (Op& op : P.ops) {
+    op.gemm.out_scale = out_scale;
+    op.idx.out_scale = out_scale;
+  }
+  const int64_t sa = ((int64_t)1 << P.pair_a.size()) * p->eb, sb = ((int64_t)1 << P.pair_b.size()) * p->eb,
+                sc = ((int64_t)1 << P.pair_out.size()) * p->eb;
+  for (int64_t i = 0; i < batch; ++i) {
+    p->ext_a = (const char*)A + i * sa;
+    p->ext_b = (const char*)B + i * sb;
+    p->ext_c = (char*)C + i * sc;
+    for (const Op& op : P.ops) {
+      int rc = launch_op(p, op, s);
+      if (rc) return rc;
+    }
+  }
+  p->last_stream = s;
+  p->ran = true;
+  return TN_OK;
+}
+
 int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream) {
   if (!p) return fail(TN_E_ARG, "plan is NULL");
+  if (p->core.pair_mode) return fail(TN_E_ARG, "pairwise plan: use tn_pair_run");
   if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
   if (!amp) return fail(TN_E_ARG, "amp is NULL");
   const int64_t ns = p->core.stats.n_slices;

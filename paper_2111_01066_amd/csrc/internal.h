@@ -13,6 +13,7 @@ namespace tnrcs {
 
 constexpr int kMaxRank = 48;  // bits of a device tensor index
 constexpr int kMaxRuns = 48;  // runs of a bit-deposit map
+constexpr int kSkinnyMaxLog2 = 12;  // the skewed kernel keeps 2^(nK+nN) <= 2^12 B entries in LDS
 
 // Bit-deposit map: value bit (src + i) goes to target bit (dst + i) for
 // i < len, for each run.  Built from "value bit j -> target position pos[j]".
@@ -25,7 +26,7 @@ struct Runs {
 
 bool make_runs(const std::vector<int>& pos, Runs* r);  // false if too many runs
 
-enum Region : int32_t { kArena = 0, kLeaves = 1, kBound = 2 };
+enum Region : int32_t { kArena = 0, kLeaves = 1, kBound = 2, kExtA = 3, kExtB = 4, kExtC = 5 };
 
 struct TRef {
   int32_t region = kArena;
@@ -138,10 +139,22 @@ struct PlanCore {
   AccumDesc accum;
   int64_t arena_elems = 0;
   int32_t root_is_leaf = 0;
+  std::vector<int> root_layout;  // layout of the final tensor (wires, most significant first)
   int32_t n_slots = 0;  // producing ops with a magnitude record (scaled storage)
   tn_plan_stats stats{};
   std::string json;
+
+  // pairwise-contraction mode (one step A x B -> C over caller buffers)
+  bool pair_mode = false;
+  std::vector<int> pair_a, pair_b, pair_out;  // index labels, most significant first
 };
+
+// Plans one pairwise contraction of caller tensors with the given index
+// labels (most significant first); the result is left in kExtC in the order
+// of `out` (a permute is appended when the step's natural layout differs).
+int build_pair_plan(PlanCore& P, std::string& err);
+// (Re)writes P.json from the current plan.
+void make_json(PlanCore& P);
 
 // Planner entry (host only).  Returns TN_OK or an error code with a message.
 int build_plan(PlanCore& P, std::string& err);

@@ -32,6 +32,9 @@ hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, in
                             float* maxslot);
 hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
                           hipStream_t s);
+// skewed contraction with B and A's K offsets in LDS (nN <= 4, nK + nN <= kSkinnyMaxLog2)
+hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
+                         hipStream_t s);
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s);
 int64_t splitk_blocks(const IndexOp& op);

@@ -82,45 +82,69 @@ struct PermArgs {
   Runs id_out;    // tile id -> output offset
 };
 
-__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Tile of 2^TB elements, 256 threads, 2^TB / 256 elements per thread; all of
+// Both global sides move 16-byte groups of G = 16 / sizeof(E) adjacent
+// elements: input positions 0..log2(G)-1 and output positions 0..log2(G)-1
+// are always in the tile, so a group is adjacent in memory on the read side
+// (in e order) and on the write side (in f order).  LDS padding of G
+// elements per 32 keeps groups adjacent and 16-byte aligned while spreading
+// power-of-two strides over the banks.
+template <int G>
+__device__ __forceinline__ int lds_pad(int e) {
+  return e + (e >> 5) * G;
+}
+
+// Tile of 2^TB elements, 256 threads, 2^TB / 256 elements per thread.  All of
 // a thread's loads are issued before any LDS store so they are in flight
-// together.  The per-element parts of the offsets that depend only on the
-// unrolled iteration are tabulated once in LDS.
+// together; the writes are streaming (non-temporal) stores.  The parts of
+// the offsets that depend only on the unrolled iteration are tabulated once
+// in LDS.
 template <int TB, typename E>
 __global__ __launch_bounds__(kPermThreads) void k_permute(const E* __restrict__ in, E* __restrict__ out,
                                                          const PermArgs a) {
+  constexpr int G = 16 / sizeof(E);
   constexpr int NT = 1 << TB;
-  constexpr int PER = NT / kPermThreads;
-  __shared__ E tile[NT + NT / 16];
-  __shared__ uint64_t hi_in[PER], hi_out[PER];
-  __shared__ int hi_fe[PER];
+  constexpr int PG = NT / kPermThreads / G;  // groups per thread
+  __shared__ __attribute__((aligned(16))) E tile[NT + (NT / 32) * G];
+  __shared__ uint64_t hi_in[PG], hi_out[PG];
+  __shared__ int hi_fe[PG];
+  __shared__ int fe_low[G];
   const int tid = threadIdx.x;
-  if (tid < PER) {
-    hi_in[tid] = dep((uint64_t)tid * kPermThreads, a.in_tile);
-    hi_out[tid] = dep((uint64_t)tid * kPermThreads, a.out_tile);
-    hi_fe[tid] = (int)dep((uint64_t)tid * kPermThreads, a.f2e);
+  if (tid < PG) {
+    hi_in[tid] = dep((uint64_t)tid * G * kPermThreads, a.in_tile);
+    hi_out[tid] = dep((uint64_t)tid * G * kPermThreads, a.out_tile);
+    hi_fe[tid] = (int)dep((uint64_t)tid * G * kPermThreads, a.f2e);
   }
+  if (tid < G) fe_low[tid] = (int)dep((uint64_t)tid, a.f2e);
   const E* src = in + (int64_t)blockIdx.y * a.stride;
   E* dst = out + (int64_t)blockIdx.y * a.stride;
-  const uint64_t e_t = dep((uint64_t)tid, a.in_tile);
-  const uint64_t f_t = dep((uint64_t)tid, a.out_tile);
-  const int fe_t = (int)dep((uint64_t)tid, a.f2e);
+  const uint64_t e_t = dep((uint64_t)tid * G, a.in_tile);
+  const uint64_t f_t = dep((uint64_t)tid * G, a.out_tile);
+  const int fe_t = (int)dep((uint64_t)tid * G, a.f2e);
   __syncthreads();
+  int fl[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) fl[g] = fe_low[g];
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const uint64_t ib = dep((uint64_t)t, a.id_in) | e_t;
     const uint64_t ob = dep((uint64_t)t, a.id_out) | f_t;
-    E v[PER];
+    u32x4 v[PG];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) v[i] = src[ib | hi_in[i]];
+    for (int i = 0; i < PG; ++i) v[i] = *reinterpret_cast<const u32x4*>(src + (ib | hi_in[i]));
 #pragma unroll
-    for (int i = 0; i < PER; ++i) tile[lds_pad(i * kPermThreads + tid)] = v[i];
+    for (int i = 0; i < PG; ++i) *reinterpret_cast<u32x4*>(&tile[lds_pad<G>(G * (i * kPermThreads + tid))]) = v[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER; ++i) v[i] = tile[lds_pad(fe_t | hi_fe[i])];
+    for (int i = 0; i < PG; ++i) {
+      const int e0 = fe_t | hi_fe[i];
+      E w[G];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) dst[ob | hi_out[i]] = v[i];
+      for (int g = 0; g < G; ++g) w[g] = tile[lds_pad<G>(e0 | fl[g])];
+      u32x4 x;
+      __builtin_memcpy(&x, w, 16);
+      __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dst + (ob | hi_out[i])));
+    }
     __syncthreads();
   }
 }
@@ -138,12 +162,6 @@ __global__ __launch_bounds__(256) void k_permute_small(const E* __restrict__ in,
 template <typename E>
 static void launch_perm_tb(int tb, dim3 g, const E* in, E* out, const PermArgs& A, hipStream_t s) {
   switch (tb) {
-    case 8:
-      hipLaunchKernelGGL((k_permute<8, E>), g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
-    case 9:
-      hipLaunchKernelGGL((k_permute<9, E>), g, dim3(kPermThreads), 0, s, in, out, A);
-      break;
     case 10:
       hipLaunchKernelGGL((k_permute<10, E>), g, dim3(kPermThreads), 0, s, in, out, A);
       break;
@@ -168,7 +186,7 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
   if (batch > 65535) return hipErrorInvalidValue;
   PermArgs A{};
   A.stride = (int64_t)1 << rank;
-  if (rank < 8) {
+  if (rank < 10) {
     // out index f: output position q holds input bit perm[q]
     std::vector<int> po, pi;
     for (int q = 0; q < rank; ++q) po.push_back(q);
@@ -223,7 +241,7 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
   if (!make_runs(p1, &A.in_tile) || !make_runs(p2, &A.out_tile) || !make_runs(p3, &A.f2e) ||
       !make_runs(p4, &A.id_in) || !make_runs(p5, &A.id_out))
     return hipErrorInvalidValue;
-  if (A.tbits < 8 || A.tbits > kPermTileBits) return hipErrorInvalidValue;
+  if (A.tbits < 10 || A.tbits > kPermTileBits) return hipErrorInvalidValue;
   const int64_t grid = std::min<int64_t>(A.n_tiles, 16384);
   const dim3 g((unsigned)grid, (unsigned)batch);
   if (elem_bytes == 8)
@@ -276,6 +294,98 @@ hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, cons
     hipLaunchKernelGGL(k_generic<float2>, g, dim3(256), 0, s, (const float2*)A, (const float2*)B, (float2*)C, op,
                        maxslot);
   return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- skinny --
+// Skewed contraction (M large, N and K small; Supplement, CPU-architecture
+// section: the small operand stays in fast local memory and the large one is
+// read once): B (2^(nK+nN) <= 4096 entries) and A's K offsets are staged in
+// LDS; each thread owns one m, streams its A row once (consecutive threads
+// take consecutive m, so A is read coalesced wherever A's low bits are M
+// bits) and keeps its 2^nN outputs in registers; C row m is written once as
+// one contiguous run of 2^nN entries.
+
+template <int NN, typename E>
+__global__ __launch_bounds__(256) void k_skinny(const E* __restrict__ A, const E* __restrict__ B, E* __restrict__ C,
+                                               const IndexOp op, float* maxslot) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int nk = 1 << op.nK;
+  float2* Bs = reinterpret_cast<float2*>(smem);                                  // [nk][NN]
+  uint64_t* kofs = reinterpret_cast<uint64_t*>(smem + (size_t)nk * NN * sizeof(float2));  // [nk]
+  for (int i = threadIdx.x; i < nk * NN; i += blockDim.x) {
+    const int k = i / NN, n = i % NN;
+    Bs[i] = to_f2(B[dep((uint64_t)n, op.bN) | dep((uint64_t)k, op.bK)]);
+  }
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) kofs[k] = dep((uint64_t)k, op.aK);
+  __syncthreads();
+  const int64_t nm = (int64_t)1 << op.nM;
+  float mx = 0.f;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t am = dep((uint64_t)m, op.aM);
+    float re[NN], im[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) re[n] = im[n] = 0.f;
+    for (int k = 0; k < nk; ++k) {
+      const float2 x = to_f2(A[am | kofs[k]]);
+      const float2* b = Bs + k * NN;
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        const float2 y = b[n];
+        re[n] = fmaf(x.x, y.x, re[n]);
+        re[n] = fmaf(-x.y, y.y, re[n]);
+        im[n] = fmaf(x.x, y.y, im[n]);
+        im[n] = fmaf(x.y, y.x, im[n]);
+      }
+    }
+    E* c = C + m * NN;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      mx = fmaxf(mx, fmaxf(fabsf(re[n]), fabsf(im[n])));
+      c[n] = from_f2<E>(re[n] * op.out_scale, im[n] * op.out_scale);
+    }
+  }
+  record_max(maxslot, mx);
+}
+
+size_t skinny_lds_bytes(const IndexOp& op) {
+  const size_t nk = (size_t)1 << op.nK, nn = (size_t)1 << op.nN;
+  return nk * nn * sizeof(float2) + nk * sizeof(uint64_t);
+}
+
+template <typename E>
+static hipError_t launch_skinny_t(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  const int64_t nm = (int64_t)1 << op.nM;
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((nm + 255) / 256, 8192)));
+  const size_t lds = skinny_lds_bytes(op);
+  switch (op.nN) {
+    case 0:
+      hipLaunchKernelGGL((k_skinny<1, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_skinny<2, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_skinny<4, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_skinny<8, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_skinny<16, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
+                         hipStream_t s) {
+  if (op.nN > 4 || op.nK + op.nN > kSkinnyMaxLog2) return hipErrorInvalidValue;
+  if (dtype == TN_DTYPE_F16S) return launch_skinny_t<cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, op, maxslot, s);
+  if (dtype == TN_DTYPE_BF16S)
+    return launch_skinny_t<cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, op, maxslot, s);
+  return launch_skinny_t<float2>((const float2*)A, (const float2*)B, (float2*)C, op, maxslot, s);
 }
 
 // ---------------------------------------------------------------- split-K --

@@ -235,10 +235,117 @@ static void add_stats_step(PlanCore& P, int nM, int nN, int nK, int ra, int rb, 
   if (nK < 64) P.stats.k_hist[nK]++;
 }
 
+void make_json(PlanCore& P) {
+  const int L = P.n_leaves;
+  std::ostringstream js;
+  js << "{\"n_leaves\":" << L << ",\"n_wires\":" << P.n_wires << ",\"arena_elems\":" << P.arena_elems
+     << ",\"leaves_elems\":" << P.leaves_elems << ",\"bound_elems\":" << P.bound_elems << ",\"open_wires\":";
+  json_vec(js, P.open_wires);
+  js << ",\"dev_leaves\":[";
+  for (size_t i = 0; i < P.dev_leaves.size(); ++i) {
+    auto& d = P.dev_leaves[i];
+    js << (i ? "," : "") << "{\"ssa\":" << d.ssa << ",\"layout\":";
+    json_vec(js, d.layout);
+    js << ",\"n_sliced\":" << d.n_sliced << ",\"slice_bit\":";
+    json_vec(js, d.slice_bit);
+    js << ",\"stored_off\":" << d.stored_off << ",\"bound_off\":" << d.bound_off << "}";
+  }
+  js << "],\"binds\":[";
+  for (size_t i = 0; i < P.binds.size(); ++i) {
+    auto& b = P.binds[i];
+    js << (i ? "," : "") << "{\"src\":" << b.src_off << ",\"dst\":" << b.dst_off << ",\"n\":" << b.n_elems
+       << ",\"sbit\":[";
+    for (int j = 0; j < b.n_sl; ++j) js << (j ? "," : "") << b.sbit[j];
+    js << "],\"pos\":[";
+    for (int j = 0; j < b.n_sl; ++j) js << (j ? "," : "") << b.pos[j];
+    js << "]}";
+  }
+  js << "],\"ops\":[";
+  for (size_t i = 0; i < P.ops.size(); ++i) {
+    const Op& op = P.ops[i];
+    js << (i ? "," : "") << "{\"kind\":" << op.kind << ",\"step\":" << op.step << ",\"flops\":" << op.flops
+       << ",\"bytes\":" << op.bytes << ",\"a\":";
+    json_ref(js, op.a);
+    js << ",\"b\":";
+    json_ref(js, op.b);
+    js << ",\"c\":";
+    json_ref(js, op.c);
+    if (op.kind == kOpPermute) {
+      js << ",\"rank\":" << op.perm.rank << ",\"perm\":[";
+      for (int q = 0; q < op.perm.rank; ++q) js << (q ? "," : "") << op.perm.perm[q];
+      js << "]";
+    } else if (op.kind == kOpGemm) {
+      js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
+         << ",\"split_k\":" << op.gemm.split_k << ",\"s_out\":" << op.s_out << ",\"w\":";
+      json_ref(js, op.w);
+    } else {
+      js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
+      json_runs(js, op.idx.aM);
+      js << ",\"aK\":";
+      json_runs(js, op.idx.aK);
+      js << ",\"bN\":";
+      json_runs(js, op.idx.bN);
+      js << ",\"bK\":";
+      json_runs(js, op.idx.bK);
+      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK << ",\"s_out\":" << op.s_out << ",\"w\":";
+      json_ref(js, op.w);
+    }
+    js << "}";
+  }
+  js << "],\"accum\":{\"n_open\":" << P.accum.n_open << ",\"root\":";
+  json_ref(js, P.accum.root);
+  js << ",\"y2root\":";
+  json_runs(js, P.accum.y2root);
+  js << "}}";
+  P.json = js.str();
+}
+
+static int build_pair_network(PlanCore& P, std::vector<HostTensor>& leaves, std::string& err) {
+  leaves.assign(2, HostTensor{});
+  leaves[0].wires = P.pair_a;
+  leaves[1].wires = P.pair_b;
+  int mx = -1;
+  for (const auto* v : {&P.pair_a, &P.pair_b, &P.pair_out})
+    for (int w : *v) {
+      if (w < 0 || w > 4095) {
+        err = "index label out of range";
+        return TN_E_ARG;
+      }
+      mx = std::max(mx, w);
+    }
+  for (const auto* v : {&P.pair_a, &P.pair_b}) {
+    std::vector<int> t = *v;
+    std::sort(t.begin(), t.end());
+    if (std::adjacent_find(t.begin(), t.end()) != t.end()) {
+      err = "repeated index label within one tensor";
+      return TN_E_ARG;
+    }
+  }
+  std::vector<int> expect;
+  for (int w : P.pair_a)
+    if (!contains(P.pair_b, w)) expect.push_back(w);
+  for (int w : P.pair_b)
+    if (!contains(P.pair_a, w)) expect.push_back(w);
+  std::vector<int> got = P.pair_out;
+  std::sort(expect.begin(), expect.end());
+  std::sort(got.begin(), got.end());
+  if (expect != got) {
+    err = "output labels must be exactly the labels of A and B that are not shared";
+    return TN_E_TOPOLOGY;
+  }
+  P.n_wires = mx + 1;
+  P.n_leaves = 2;
+  P.leaf_wires = {P.pair_a, P.pair_b};
+  P.open_wires = P.pair_out;
+  P.pairs = {0, 1};
+  P.sliced.clear();
+  return TN_OK;
+}
+
 int build_plan(PlanCore& P, std::string& err) {
   const int n = P.n_qubits;
   std::vector<HostTensor> leaves;
-  int rc = build_network(P, leaves, err);
+  int rc = P.pair_mode ? build_pair_network(P, leaves, err) : build_network(P, leaves, err);
   if (rc) return rc;
   const int L = P.n_leaves;
   const int S = (int)P.pairs.size() / 2;
@@ -354,7 +461,7 @@ int build_plan(PlanCore& P, std::string& err) {
     }
     d.n_sliced = (int)sl.size();
     d.layout.insert(d.layout.end(), rest.begin(), rest.end());
-    d.data = relayout(ht[ssa].data, ht[ssa].wires, d.layout);
+    if (!P.pair_mode) d.data = relayout(ht[ssa].data, ht[ssa].wires, d.layout);
     devleaf_of[ssa] = (int)P.dev_leaves.size();
     P.dev_leaves.push_back(std::move(d));
   };
@@ -380,7 +487,7 @@ int build_plan(PlanCore& P, std::string& err) {
   P.bound_elems = 0;
   P.binds.clear();
   for (auto& d : P.dev_leaves) {
-    int64_t ne = (int64_t)d.data.size();
+    int64_t ne = P.pair_mode ? 0 : (int64_t)d.data.size();
     d.stored_off = P.leaves_elems;
     P.leaves_elems += align_up(ne, 64);
     if (d.n_sliced > 0) {
@@ -405,7 +512,9 @@ int build_plan(PlanCore& P, std::string& err) {
   std::vector<TRef> where(L + S);
   for (auto& d : P.dev_leaves) {
     lay[d.ssa] = std::vector<int>(d.layout.begin() + d.n_sliced, d.layout.end());
-    if (d.n_sliced > 0)
+    if (P.pair_mode)
+      where[d.ssa] = TRef{d.ssa == 0 ? kExtA : kExtB, 0};
+    else if (d.n_sliced > 0)
       where[d.ssa] = TRef{kBound, d.bound_off};
     else
       where[d.ssa] = TRef{kLeaves, d.stored_off};
@@ -560,7 +669,10 @@ int build_plan(PlanCore& P, std::string& err) {
     } else {
       Op g;
       const bool splitk = (nM + nN) <= 6 && nK >= 10;
-      g.kind = splitk ? kOpSplitK : kOpGeneric;
+      // skewed (Supplement, CPU-architecture section): the small operand
+      // fits in LDS, few outputs per row of the large one
+      const bool skinny = !splitk && nN <= 4 && nK + nN <= kSkinnyMaxLog2 && nM >= 8;
+      g.kind = splitk ? kOpSplitK : (skinny ? kOpSkinny : kOpGeneric);
       g.step = t;
       g.idx.nM = nM;
       g.idx.nN = nN;
@@ -599,7 +711,10 @@ int build_plan(PlanCore& P, std::string& err) {
       g.ssa_c = L + t;
       if (half) g.max_slot = P.n_slots++;
       P.ops.push_back(g);
-      P.stats.n_generic++;
+      if (skinny)
+        P.stats.n_skinny++;
+      else
+        P.stats.n_generic++;
     }
     dstep++;
   }
@@ -621,6 +736,7 @@ int build_plan(PlanCore& P, std::string& err) {
   // final accumulation
   P.accum = AccumDesc{};
   P.accum.n_open = (int)P.open_wires.size();
+  P.root_layout = lay[root];
   {
     const std::vector<int>& Lr = lay[root];
     std::vector<int> p;
@@ -651,68 +767,7 @@ int build_plan(PlanCore& P, std::string& err) {
   st.n_open = (int)P.open_wires.size();
   st.arena_bytes = P.arena_elems * elem_bytes_plan(P);
   st.leaf_bytes = (P.leaves_elems + P.bound_elems) * elem_bytes_plan(P);
-  // JSON
-  std::ostringstream js;
-  js << "{\"n_leaves\":" << L << ",\"n_wires\":" << P.n_wires << ",\"arena_elems\":" << P.arena_elems
-     << ",\"leaves_elems\":" << P.leaves_elems << ",\"bound_elems\":" << P.bound_elems << ",\"open_wires\":";
-  json_vec(js, P.open_wires);
-  js << ",\"dev_leaves\":[";
-  for (size_t i = 0; i < P.dev_leaves.size(); ++i) {
-    auto& d = P.dev_leaves[i];
-    js << (i ? "," : "") << "{\"ssa\":" << d.ssa << ",\"layout\":";
-    json_vec(js, d.layout);
-    js << ",\"n_sliced\":" << d.n_sliced << ",\"slice_bit\":";
-    json_vec(js, d.slice_bit);
-    js << ",\"stored_off\":" << d.stored_off << ",\"bound_off\":" << d.bound_off << "}";
-  }
-  js << "],\"binds\":[";
-  for (size_t i = 0; i < P.binds.size(); ++i) {
-    auto& b = P.binds[i];
-    js << (i ? "," : "") << "{\"src\":" << b.src_off << ",\"dst\":" << b.dst_off << ",\"n\":" << b.n_elems
-       << ",\"sbit\":[";
-    for (int j = 0; j < b.n_sl; ++j) js << (j ? "," : "") << b.sbit[j];
-    js << "],\"pos\":[";
-    for (int j = 0; j < b.n_sl; ++j) js << (j ? "," : "") << b.pos[j];
-    js << "]}";
-  }
-  js << "],\"ops\":[";
-  for (size_t i = 0; i < P.ops.size(); ++i) {
-    const Op& op = P.ops[i];
-    js << (i ? "," : "") << "{\"kind\":" << op.kind << ",\"step\":" << op.step << ",\"flops\":" << op.flops
-       << ",\"bytes\":" << op.bytes << ",\"a\":";
-    json_ref(js, op.a);
-    js << ",\"b\":";
-    json_ref(js, op.b);
-    js << ",\"c\":";
-    json_ref(js, op.c);
-    if (op.kind == kOpPermute) {
-      js << ",\"rank\":" << op.perm.rank << ",\"perm\":[";
-      for (int q = 0; q < op.perm.rank; ++q) js << (q ? "," : "") << op.perm.perm[q];
-      js << "]";
-    } else if (op.kind == kOpGemm) {
-      js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
-         << ",\"split_k\":" << op.gemm.split_k << ",\"s_out\":" << op.s_out << ",\"w\":";
-      json_ref(js, op.w);
-    } else {
-      js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
-      json_runs(js, op.idx.aM);
-      js << ",\"aK\":";
-      json_runs(js, op.idx.aK);
-      js << ",\"bN\":";
-      json_runs(js, op.idx.bN);
-      js << ",\"bK\":";
-      json_runs(js, op.idx.bK);
-      js << ",\"tM\":" << op.idx.tM << ",\"tK\":" << op.idx.tK << ",\"s_out\":" << op.s_out << ",\"w\":";
-      json_ref(js, op.w);
-    }
-    js << "}";
-  }
-  js << "],\"accum\":{\"n_open\":" << P.accum.n_open << ",\"root\":";
-  json_ref(js, P.accum.root);
-  js << ",\"y2root\":";
-  json_runs(js, P.accum.y2root);
-  js << "}}";
-  P.json = js.str();
+  make_json(P);
   (void)n;
   return TN_OK;
 }
@@ -740,6 +795,40 @@ void propagate_exponents(PlanCore& P) {
   for (const Op& op : P.ops)
     if (op.ssa_c >= 0) e[op.ssa_c] = e[op.ssa_a] + e[op.ssa_b] + op.s_out;
   P.accum.root_scale = std::ldexp(1.0, e.count(P.accum.root_ssa) ? e[P.accum.root_ssa] : 0);
+}
+
+int build_pair_plan(PlanCore& P, std::string& err) {
+  P.pair_mode = true;
+  P.opts.host_fold_log2 = 0;
+  int rc = build_plan(P, err);
+  if (rc) return rc;
+  // the op that wrote the root
+  int last = -1;
+  for (int i = 0; i < (int)P.ops.size(); ++i)
+    if (P.ops[i].c.region == kArena && P.ops[i].c.off == P.accum.root.off && P.ops[i].kind != kOpPermute) last = i;
+  if (last < 0) {
+    err = "internal: pair plan without a producing op";
+    return TN_E_UNSUPPORTED;
+  }
+  if (P.root_layout == P.pair_out) {
+    P.ops[last].c = TRef{kExtC, 0};
+  } else {
+    Op op;
+    op.kind = kOpPermute;
+    op.step = 0;
+    const int r = (int)P.pair_out.size();
+    op.perm.rank = r;
+    for (int q = 0; q < r; ++q) op.perm.perm[q] = pos_in(P.root_layout, P.pair_out[r - 1 - q]);
+    op.a = P.accum.root;
+    op.c = TRef{kExtC, 0};
+    op.bytes = 2.0 * elem_bytes_plan(P) * std::ldexp(1.0, r);
+    P.ops.push_back(op);
+    P.stats.n_permute++;
+    P.stats.moved_per_slice += op.bytes;
+  }
+  P.stats.n_kernels = (int)P.ops.size();
+  make_json(P);
+  return TN_OK;
 }
 
 int refold_leaves(PlanCore& P, std::string& err) {

@@ -22,6 +22,13 @@ LIB_PATH = os.path.join(_HERE, "libtnrcs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2111_01066_amd.build.build() "
                       "(hipcc, gfx950) before using the library")
+# PyTorch ships its own HIP runtime; load it first so that the library binds
+# to the same runtime instance (two runtimes in one process do not share
+# devices, streams or memory).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 TN_OK = 0
@@ -76,6 +83,9 @@ _lib.tn_plan_set_output_bits.argtypes = [c_void_p, POINTER(c_uint8)]
 _lib.tn_plan_destroy.argtypes = [c_void_p]
 _lib.tn_plan_profile.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, POINTER(ctypes.c_float), c_int32,
                                  POINTER(c_int32)]
+_lib.tn_pair_plan.argtypes = [c_int32, POINTER(c_int32), c_int32, POINTER(c_int32), c_int32, POINTER(c_int32),
+                              POINTER(tn_plan_opts), POINTER(c_void_p)]
+_lib.tn_pair_run.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p]
 _lib.tn_permute.argtypes = [c_void_p, c_void_p, c_int32, c_int32, POINTER(c_int32), c_int64, c_void_p]
 _lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                                ctypes.c_float, c_void_p, c_int32, c_void_p, c_void_p]
@@ -86,7 +96,7 @@ _lib.tn_amp_xeb.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_vo
 _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_void_p, c_void_p]
 
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
-            "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error",
+            "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
             "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
 
 
@@ -231,6 +241,40 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class PairPlan:
+    """Owns a pairwise-contraction plan (tn_pair_plan / tn_pair_run)."""
+
+    def __init__(self, labels_a, labels_b, labels_c, dtype: str = "c64", gemm_form: str = "auto",
+                 dry_run: bool = False, device: int = 0):
+        self._h = None
+        o = tn_plan_opts_default()
+        o.dtype = DTYPES[dtype]
+        o.gemm_form = GEMM_FORMS[gemm_form]
+        o.dry_run = int(dry_run)
+        o.device = int(device)
+        h = c_void_p()
+        _check(_lib.tn_pair_plan(len(labels_a), _i32(labels_a), len(labels_b), _i32(labels_b), len(labels_c),
+                                 _i32(labels_c), byref(o), byref(h)))
+        self._h = h
+
+    def run(self, A, B, C, batch: int = 1, out_scale: float = 1.0, stream=None):
+        _check(_lib.tn_pair_run(self._h, c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(batch),
+                                float(out_scale), c_void_p(_stream(stream))))
+
+    info = Plan.info
+    json = Plan.json
+    close = Plan.close
+    __del__ = Plan.__del__
+
+
+def tn_pair_plan(labels_a, labels_b, labels_c, **kw) -> PairPlan:
+    return PairPlan(labels_a, labels_b, labels_c, **kw)
+
+
+def tn_pair_run(pp: PairPlan, A, B, C, batch: int = 1, out_scale: float = 1.0, stream=None):
+    pp.run(A, B, C, batch, out_scale, stream)
 
 
 def tn_plan(circuit, pairs, sliced=(), open_qubits=(), out_bits=None, **kw) -> Plan:

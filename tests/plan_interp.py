@@ -27,9 +27,16 @@ class PlanInterpreter:
         self.bound = np.full(js["bound_elems"], np.nan, dtype=np.complex128)
         self.arena = np.full(js["arena_elems"], np.nan, dtype=np.complex128)
 
+    ext = {}
+
     def region(self, ref):
         reg, off = ref
+        if reg >= 3:
+            return self.ext[reg], off
         return {0: self.arena, 1: self.leaves, 2: self.bound}[reg], off
+
+    def run_ops(self):
+        self._ops(self.js["ops"])
 
     def run_slice(self, s, amp):
         js = self.js
@@ -38,7 +45,16 @@ class PlanInterpreter:
             for sb, p in zip(b["sbit"], b["pos"]):
                 off |= ((s >> sb) & 1) << p
             self.bound[b["dst"]:b["dst"] + b["n"]] = self.leaves[b["src"] + off:b["src"] + off + b["n"]]
-        for op in js["ops"]:
+        self._ops(js["ops"])
+        acc = js["accum"]
+        rr, orr = self.region(acc["root"])
+        y = np.arange(1 << acc["n_open"])
+        v = rr[orr + dep(y, acc["y2root"])]
+        assert not np.isnan(v).any()
+        amp += v
+
+    def _ops(self, ops):
+        for op in ops:
             ra, oa = self.region(op["a"])
             rc, oc = self.region(op["c"])
             if op["kind"] == 0:  # permute
@@ -67,9 +83,3 @@ class PlanInterpreter:
                 B = rb[ob + Bi]
                 assert not np.isnan(A).any() and not np.isnan(B).any()
                 rc[oc:oc + (1 << (nM + nN))] = (A @ B.T).reshape(-1)
-        acc = js["accum"]
-        rr, orr = self.region(acc["root"])
-        y = np.arange(1 << acc["n_open"])
-        v = rr[orr + dep(y, acc["y2root"])]
-        assert not np.isnan(v).any()
-        amp += v

@@ -110,3 +110,20 @@ def test_disconnected_network_product_state():
     leaves, ow = oracle.build_network(c, open_q, None)
     a = oracle.contract_network(leaves, pairs, ow)
     np.testing.assert_allclose(a, oracle.statevector(c).reshape(-1), atol=1e-14)
+
+
+def test_contract_entries_matches_pairwise():
+    rng = np.random.default_rng(11)
+    la, lb, lc = [4, 0, 7, 2, 9], [7, 3, 4, 1], [9, 3, 0, 2, 1]
+    A = rng.normal(size=(2,) * 5) + 1j * rng.normal(size=(2,) * 5)
+    B = rng.normal(size=(2,) * 4) + 1j * rng.normal(size=(2,) * 4)
+    C, wc = oracle.pairwise_contract(A, la, B, lb)
+    C = np.transpose(C, [wc.index(l) for l in lc])
+    coords = np.array(list(itertools.product(range(2), repeat=5)))
+    got = oracle.tn.contract_entries(A, la, B, lb, lc, coords)
+    np.testing.assert_allclose(got, C.reshape(-1), atol=1e-13)
+    # no shared index: outer product
+    got = oracle.tn.contract_entries(A[..., 0, 0], [4, 0, 7], B[0, 0], [3, 1], [4, 0, 7, 3, 1],
+                                     coords[:, :5])
+    ref = np.einsum("abc,de->abcde", A[..., 0, 0], B[0, 0]).reshape(-1)
+    np.testing.assert_allclose(got, ref, atol=1e-13)

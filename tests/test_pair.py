@@ -1,0 +1,142 @@
+"""Pairwise contraction entry point (tn_pair_plan / tn_pair_run): CPU dry-run
+interpretation vs numpy, and GPU parity (complex64 and scaled FP16), including
+the rank-27 x rank-25 microbench shape on sampled outputs vs the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_01066_amd import tnrcs
+from rqcgen.workloads import config2_pair
+from tests.plan_interp import PlanInterpreter
+
+# (labels A, labels B, labels C): dense, skinny, split-K, generic, outer product
+CASES = [
+    ([0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11], [12, 13, 14, 15, 16, 17, 18, 5, 6, 7, 8, 9, 10, 11],
+     [0, 1, 2, 3, 4, 12, 13, 14, 15, 16, 17, 18]),
+    ([3, 0, 8, 1, 9, 2, 10, 4, 11, 5, 12, 6], [6, 20, 0, 21], [3, 8, 1, 9, 2, 10, 4, 11, 5, 12, 20, 21]),
+    ([0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12], [13, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11],
+     [12, 13]),
+    ([5, 1, 7, 3], [3, 8, 5, 9], [9, 7, 8, 1]),
+    ([0, 1, 2], [3, 4], [3, 0, 4, 1, 2]),
+]
+
+
+def _rand(rng, r):
+    return rng.standard_normal(1 << r) + 1j * rng.standard_normal(1 << r)
+
+
+def _ref(A, la, B, lb, lc):
+    C, wc = oracle.pairwise_contract(A.reshape((2,) * len(la)), la, B.reshape((2,) * len(lb)), lb)
+    return np.transpose(C, [wc.index(l) for l in lc]).reshape(-1) if lc else C.reshape(-1)
+
+
+@pytest.mark.parametrize("la,lb,lc", CASES)
+def test_pair_dryrun(la, lb, lc):
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+    rng = np.random.default_rng(len(la) * 7 + len(lb))
+    A, B = _rand(rng, len(la)), _rand(rng, len(lb))
+    it = PlanInterpreter.__new__(PlanInterpreter)
+    it.js = pp.json()
+    it.arena = np.full(it.js["arena_elems"], np.nan, dtype=np.complex128)
+    it.leaves = it.bound = np.zeros(0, dtype=np.complex128)
+    C = np.full(1 << len(lc), np.nan, dtype=np.complex128)
+    it.ext = {3: A, 4: B, 5: C}
+    it.run_ops()
+    np.testing.assert_allclose(C, _ref(A, la, B, lb, lc), atol=1e-12)
+    pp.close()
+
+
+def test_pair_rejects_bad_labels():
+    with pytest.raises(tnrcs.TnError):
+        tnrcs.PairPlan([0, 1], [1, 2], [0], dry_run=True)
+    with pytest.raises(tnrcs.TnError):
+        tnrcs.PairPlan([0, 0], [1, 2], [1, 2], dry_run=True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["c64", "f16s"])
+@pytest.mark.parametrize("la,lb,lc", CASES)
+def test_pair_gpu(la, lb, lc, dtype):
+    import torch
+    rng = np.random.default_rng(len(la) * 5 + len(lb))
+    A, B = _rand(rng, len(la)), _rand(rng, len(lb))
+    print(f"pair {dtype} ranks {len(la)}x{len(lb)}->{len(lc)}", flush=True)
+    pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
+    if dtype == "c64":
+        dA = torch.from_numpy(A.astype(np.complex64)).cuda()
+        dB = torch.from_numpy(B.astype(np.complex64)).cuda()
+        dC = torch.empty(1 << len(lc), dtype=torch.complex64, device="cuda")
+        pp.run(dA, dB, dC, batch=1)
+        torch.cuda.synchronize()
+        C = dC.cpu().numpy().astype(np.complex128)
+        ref = _ref(A.astype(np.complex64).astype(np.complex128), la, B.astype(np.complex64).astype(np.complex128),
+                   lb, lc)
+        tol = 1e-5
+    else:
+        def pairs(z):
+            return torch.stack([torch.from_numpy(z.real.copy()), torch.from_numpy(z.imag.copy())], -1).half().cuda()
+        dA, dB = pairs(A), pairs(B)
+        Aq = dA.float().cpu().numpy()
+        Bq = dB.float().cpu().numpy()
+        Aq, Bq = Aq[..., 0] + 1j * Aq[..., 1], Bq[..., 0] + 1j * Bq[..., 1]
+        ref = _ref(Aq, la, Bq, lb, lc)
+        scale = 2.0 ** -int(np.ceil(np.log2(np.abs(ref).max())) - 12)
+        dC = torch.empty((1 << len(lc), 2), dtype=torch.float16, device="cuda")
+        pp.run(dA, dB, dC, batch=1, out_scale=scale)
+        torch.cuda.synchronize()
+        Cq = dC.float().cpu().numpy().astype(np.float64) / scale
+        C = Cq[..., 0] + 1j * Cq[..., 1]
+        tol = 2e-3
+    assert oracle.relative_error_norm(C, ref) < tol
+    pp.close()
+
+
+@pytest.mark.gpu
+def test_config2_microbench_sampled_entries():
+    """Rank-27 x rank-25 pairs sharing 12 indices, 32 pairs per call, output in
+    a seeded random order; 512 sampled output entries per pair for 4 pairs
+    computed one by one by the oracle in FP64."""
+    import torch
+    la, lb, lc = config2_pair(seed=2)
+    n_pairs = 32
+    pp = tnrcs.PairPlan(la, lb, lc)
+    info = pp.info()
+    print(f"config 2: dense={info['n_dense']} permutes={info['n_permute']}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2)
+    s = 0.5 ** 0.5
+    A = torch.complex(torch.randn(n_pairs, 1 << 27, generator=g, device="cuda") * s,
+                      torch.randn(n_pairs, 1 << 27, generator=g, device="cuda") * s)
+    B = torch.complex(torch.randn(n_pairs, 1 << 25, generator=g, device="cuda") * s,
+                      torch.randn(n_pairs, 1 << 25, generator=g, device="cuda") * s)
+    C = torch.empty(n_pairs, 1 << 28, dtype=torch.complex64, device="cuda")
+    pp.run(A, B, C, batch=n_pairs)
+    torch.cuda.synchronize()
+    shared = [l for l in la if l in lb]
+    rng = np.random.default_rng(7)
+    for pair in (0, 9, 20, 31):
+        coords = rng.integers(0, 2, size=(512, 28))
+        # flat offsets of every (coordinate, shared assignment) in A and B
+        sh = np.array(np.meshgrid(*[[0, 1]] * 12, indexing="ij")).reshape(12, -1).T  # 4096 x 12
+        def flat(labels, c_row):
+            fixed = dict(zip(lc, c_row))
+            idx = np.zeros(4096, dtype=np.int64)
+            for pos, l in enumerate(labels):
+                w = len(labels) - 1 - pos
+                bit = sh[:, shared.index(l)] if l in shared else np.full(4096, fixed[l])
+                idx |= bit.astype(np.int64) << w
+            return idx
+        ia = np.stack([flat(la, c) for c in coords])
+        ib = np.stack([flat(lb, c) for c in coords])
+        sa = A[pair][torch.from_numpy(ia).cuda()].cpu().numpy().astype(np.complex128)
+        sb = B[pair][torch.from_numpy(ib).cuda()].cpu().numpy().astype(np.complex128)
+        ref = np.array([oracle.tn.contract_entry(sa[i].reshape((2,) * 12), shared, sb[i].reshape((2,) * 12), shared)
+                        for i in range(len(coords))])
+        oc = np.zeros(len(coords), dtype=np.int64)
+        for pos in range(28):
+            oc |= coords[:, pos].astype(np.int64) << (27 - pos)
+        got = C[pair][torch.from_numpy(oc).cuda()].cpu().numpy().astype(np.complex128)
+        err = oracle.relative_error_norm(got, ref)
+        print(f"  pair {pair}: relative error {err:.2e}", flush=True)
+        assert err < 1e-5
+    pp.close()
