@@ -3,15 +3,19 @@ circuit network (6x9 grid with one missing site, 6 open qubits -> bunches of
 64 amplitudes, every per-slice tensor <= 2^32 entries) on one MI355X.
 
 One step = one slice: bind, every pairwise contraction of the slice
-(permutes, complex GEMMs on MFMA, gathered contractions) and the FP64
-accumulation of its 64 amplitudes.  Prints one JSON line.
+(permutes, complex GEMMs on MFMA, skewed / gathered contractions) and the
+FP64 accumulation of its 64 amplitudes.  The headline line is the complex64
+network; the same network in scaled FP16 / BF16, the pairwise-contraction
+microbench (32 rank-27 x rank-25 pairs) and the permute / skewed-kernel
+bandwidths are reported alongside.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--form auto|4m|3m]
-                  [--no-cpu-baseline]
+                  [--dtype c64|f16s|bf16s] [--no-extra] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,13 +25,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sec/slice + complex TFLOP/s (% MFMA peak), 53-qubit 14-cycle synthetic RCS"
-PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
-PEAK_HBM = 8000.0       # GB/s
+PEAK = {"c64": 157.3, "f16s": 2500.0, "bf16s": 2500.0}  # dense MFMA TFLOP/s: FP32, FP16, BF16
+PEAK_HBM = 8000.0  # GB/s
 KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 4: "k_splitk", 9: "k_accum"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2111_01066_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, dtype: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_sha") != source_sha():
+        return None
+    return d.get("per_launch_bytes", {}).get(f"{kernel}:{dtype}")
+
+
+def w_flops_per_slice(w):
+    from rqcgen import network_structure, order_stats
+    return order_stats(network_structure(w.circuit, w.open_qubits), w.pairs, w.sliced).flops_per_slice
 
 
 def cpu_baseline(w, sub_log2: int):
@@ -51,10 +82,173 @@ def cpu_baseline(w, sub_log2: int):
     dt = time.perf_counter() - t0
     rate = st.flops_per_slice / dt / 1e12
     return {"value": rate, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"FP64 numpy tensordot contraction of one sub-slice of slice 0 "
+            "sample": (f"FP64 numpy tensordot contraction of one sub-slice of slice 0 of the same network "
                        f"({len(allsl) - len(w.sliced)} extra sliced wires, tensors <= 2^{sub_log2}, "
-                       f"{st.flops_per_slice:.3e} flop) in {dt:.1f} s"),
+                       f"{st.flops_per_slice:.3e} flop) in {dt:.1f} s; at this rate one slice "
+                       f"({w_flops_per_slice(w):.3e} flop) takes {w_flops_per_slice(w) / (rate * 1e12):.0f} s"),
             "seconds": dt}
+
+
+def run_network(tnrcs, torch, w, dtype, form, K, W, graph=True, profile=True):
+    t0 = time.perf_counter()
+    plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, gemm_form=form, use_graph=graph,
+                      dtype=dtype)
+    info = plan.info()
+    log(f"[bench] {dtype}: planned in {time.perf_counter() - t0:.2f} s: {info['n_device_steps']} device steps, "
+        f"{info['n_kernels']} kernels/slice, arena {info['arena_bytes'] / 2**30:.1f} GiB, "
+        f"{info['flops_per_slice']:.3e} flop/slice")
+    stream = torch.cuda.current_stream()
+    amp = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    for s in range(W):
+        plan.contract(s, s + 1, amp)
+        torch.cuda.synchronize()
+        log(f"[bench] {dtype}: warmup slice {s} done")
+    amp.zero_()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for s in range(K):
+        plan.contract(s, s + 1, amp)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    flags = plan.status()
+    res = {"plan": plan, "info": info, "sec_per_slice": gpu_s / K, "tflops": info["flops_per_slice"] * K / gpu_s / 1e12,
+           "flags": flags, "amp": amp.cpu().numpy()}
+    log(f"[bench] {dtype}: {K} slices in {gpu_s:.3f} s: {gpu_s / K:.4f} s/slice, {res['tflops']:.2f} complex "
+        f"TFLOP/s, flags={flags}")
+    if profile:
+        res["ops"] = plan.json()["ops"]
+        scratch = torch.zeros(64, dtype=torch.complex128, device="cuda")
+        res["ms"] = plan.profile(0, scratch)
+    return res
+
+
+def kernel_split(res, dtype):
+    ops, ms = res["ops"], res["ms"]
+    by_kind = {}
+    for i, t in enumerate(ms):
+        o = ops[i] if i < len(ops) else {"kind": 9, "flops": 0.0, "bytes": 0.0}
+        d = by_kind.setdefault(o["kind"], {"ms": 0.0, "n": 0, "flops": 0.0, "bytes": 0.0, "issued": 0.0})
+        d["ms"] += float(t)
+        d["n"] += 1
+        d["flops"] += o["flops"]
+        d["bytes"] += o["bytes"]
+        d["issued"] += o["flops"] * (0.75 if o.get("form") == 2 else 1.0)
+    split = {KIND_NAMES[k]: {"ms_per_slice": v["ms"], "launches": v["n"]} for k, v in by_kind.items()}
+    for k, v in by_kind.items():
+        if k in (0, 2, 3, 4) and v["ms"] > 0:
+            split[KIND_NAMES[k]]["GB/s"] = v["bytes"] / (v["ms"] / 1e3) / 1e9
+    order = sorted(range(len(ops)), key=lambda i: -ms[i])
+    for i in order[:12]:
+        o = ops[i]
+        shape = (f"M={o['M']} N={o['N']} K={o['K']}" if o["kind"] == 1 else
+                 f"rank={o['rank']}" if o["kind"] == 0 else f"nM={o['nM']} nN={o['nN']} nK={o['nK']}")
+        rate = (f"{o['flops'] / (ms[i] / 1e3) / 1e12:.1f} TFLOP/s" if o["kind"] == 1 else
+                f"{o['bytes'] / (ms[i] / 1e3) / 1e9:.0f} GB/s")
+        log(f"[bench]   {dtype} op {i:3d} {KIND_NAMES.get(o['kind'], o['kind']):10s} {ms[i]:9.3f} ms  {shape:28s} "
+            f"{rate}")
+    return by_kind, split
+
+
+def roofline(by_kind, dtype):
+    dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
+    d = by_kind[dom]
+    avg_ms = d["ms"] / d["n"]
+    name = KIND_NAMES[dom]
+    if dom == 1:
+        achieved = d["issued"] / d["n"] / (avg_ms / 1e3) / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK[dtype], "unit": "TFLOP/s",
+                "frac": achieved / PEAK[dtype], "traffic": measured_traffic(name, dtype),
+                "launches_per_slice": d["n"], "avg_ms": avg_ms, "flop_per_launch": d["issued"] / d["n"],
+                "complex_tflops": d["flops"] / d["n"] / (avg_ms / 1e3) / 1e12,
+                "note": "achieved = issued real MFMA flops per launch (6 per complex multiply-add in the 3M form, "
+                        "8 in 4M) / mean launch duration (HIP events on the launch stream); traffic = HBM bytes "
+                        "per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain copy)"}
+    achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype), "launches_per_slice": d["n"],
+            "avg_ms": avg_ms, "bytes_per_launch": d["bytes"] / d["n"]}
+
+
+def micro(tnrcs, torch, np):
+    """Standalone kernels on the shapes that matter, timed with HIP events."""
+    out = {}
+
+    def timed(fn, n=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    rng = np.random.default_rng(0)
+    r = 30
+    perm = rng.permutation(r).tolist()
+    for eb, name in ((8, "c64"), (4, "f16s")):
+        x = torch.ones(1 << r, dtype=torch.float64 if eb == 8 else torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        ms = timed(lambda: tnrcs.tn_permute(x, y, perm, elem_bytes=eb))
+        ms_copy = timed(lambda: y.copy_(x))
+        gbs, cps = 2.0 * x.numel() * eb / ms / 1e6, 2.0 * x.numel() * eb / ms_copy / 1e6
+        out[f"permute_rank30_{name}"] = {"GB/s": gbs, "frac_hbm": gbs / PEAK_HBM, "device_copy_GB/s": cps,
+                                         "frac_of_copy": gbs / cps}
+        log(f"[bench] permute rank 30 {name}: {gbs:.0f} GB/s ({gbs / PEAK_HBM:.1%} of 8 TB/s; copy {cps:.0f} GB/s)")
+        del x, y
+    # skewed contraction: a rank-30 tensor absorbing a two-qubit gate (K=2, N=2 bits)
+    la = list(range(30))
+    lb = [la[29], la[28], 100, 101]
+    lc = la[:28] + [100, 101]
+    for dtype in ("c64", "f16s"):
+        pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
+        kinds = [o["kind"] for o in pp.json()["ops"]]
+        if dtype == "c64":
+            A = torch.ones(1 << 30, dtype=torch.complex64, device="cuda")
+            B = torch.ones(16, dtype=torch.complex64, device="cuda")
+            C = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+            eb = 8
+        else:
+            A = torch.ones(1 << 30, 2, dtype=torch.float16, device="cuda")
+            B = torch.ones(16, 2, dtype=torch.float16, device="cuda")
+            C = torch.empty(1 << 30, 2, dtype=torch.float16, device="cuda")
+            eb = 4
+        ms = timed(lambda: pp.run(A, B, C, out_scale=1.0 if dtype == "c64" else 0.25))
+        gbs = eb * ((1 << 31) + 16) / ms / 1e6
+        out[f"skinny_rank30_gate_{dtype}"] = {"GB/s": gbs, "frac_hbm": gbs / PEAK_HBM, "kernels": kinds}
+        log(f"[bench] skewed contraction (rank 30 x two-qubit gate) {dtype}: {gbs:.0f} GB/s ({gbs / PEAK_HBM:.1%})")
+        pp.close()
+        del A, B, C
+    # config 2: 32 pairs of rank-27 x rank-25 complex tensors sharing 12 indices
+    from rqcgen.workloads import config2_pair
+    la, lb, lc = config2_pair(seed=2)
+    n_pairs = 32
+    for dtype in ("c64", "f16s"):
+        pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(2)
+        if dtype == "c64":
+            A = torch.randn(n_pairs, 1 << 27, dtype=torch.complex64, device="cuda", generator=g)
+            B = torch.randn(n_pairs, 1 << 25, dtype=torch.complex64, device="cuda", generator=g)
+            C = torch.empty(n_pairs, 1 << 28, dtype=torch.complex64, device="cuda")
+        else:
+            A = torch.randn(n_pairs, 1 << 27, 2, device="cuda", generator=g).half()
+            B = torch.randn(n_pairs, 1 << 25, 2, device="cuda", generator=g).half()
+            C = torch.empty(n_pairs, 1 << 28, 2, dtype=torch.float16, device="cuda")
+        ms = timed(lambda: pp.run(A, B, C, batch=n_pairs, out_scale=1.0 if dtype == "c64" else 2.0 ** -8), n=2)
+        fl = 8.0 * 2 ** 15 * 2 ** 13 * 2 ** 12 * n_pairs
+        tf = fl / ms / 1e9
+        out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
+                                          "frac_peak": tf / PEAK[dtype]}
+        log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
+            f"TFLOP/s ({tf / PEAK[dtype]:.1%} of the {dtype} MFMA peak, permutes included)")
+        pp.close()
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -65,8 +259,9 @@ def main():
     ap.add_argument("--form", default="auto", choices=["auto", "4m", "3m"])
     ap.add_argument("--dtype", default="c64", choices=["c64", "f16s", "bf16s"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the precision variants and microbenchmarks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sub-log2", type=int, default=26)
+    ap.add_argument("--cpu-sub-log2", type=int, default=28)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM-counter calibration)")
     args = ap.parse_args()
@@ -82,88 +277,15 @@ def main():
 
     w = config3()
     log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
-    t0 = time.perf_counter()
-    plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, gemm_form=args.form,
-                      use_graph=not args.no_graph, dtype=args.dtype)
-    info = plan.info()
-    log(f"[bench] planned in {time.perf_counter() - t0:.2f} s: {info['n_device_steps']} device steps, "
-        f"{info['n_kernels']} kernels/slice, arena {info['arena_bytes'] / 2**30:.1f} GiB, "
-        f"{info['flops_per_slice']:.3e} flop/slice")
-    n_slices = info["n_slices"]
-    K, W = args.steps, args.warmup
-    if K + W > n_slices:
-        K = max(1, n_slices - W)
-    stream = torch.cuda.current_stream()
-    amp = torch.zeros(64, dtype=torch.complex128, device="cuda")
-    for s in range(W):
-        plan.contract(s, s + 1, amp)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup slice {s} done")
-    amp.zero_()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for s in range(K):
-        plan.contract(s, s + 1, amp)
-        if (s + 1) % 4 == 0 or s + 1 == K:
-            log(f"[bench] timed slice {s} enqueued")
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    flags = plan.status()
-    sec_per_slice = gpu_s / K
-    tflops = info["flops_per_slice"] * K / gpu_s / 1e12
-    log(f"[bench] {K} slices in {gpu_s:.3f} s (wall {wall:.3f} s): {sec_per_slice:.4f} s/slice, "
-        f"{tflops:.2f} complex TFLOP/s, flags={flags}")
-
-    # per-kernel durations of one slice (HIP events on the launch stream)
-    ops = plan.json()["ops"]
-    scratch = torch.zeros(64, dtype=torch.complex128, device="cuda")
-    ms = plan.profile(0, scratch)
-    kinds = [o["kind"] for o in ops] + [9]
-    flops = [o["flops"] for o in ops] + [0.0]
-    byts = [o["bytes"] for o in ops] + [64 * 8.0]
-    by_kind = {}
-    for k, t, f, b in zip(kinds, ms, flops, byts):
-        d = by_kind.setdefault(k, {"ms": 0.0, "n": 0, "flops": 0.0, "bytes": 0.0})
-        d["ms"] += float(t)
-        d["n"] += 1
-        d["flops"] += f
-        d["bytes"] += b
-    dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
-    d = by_kind[dom]
-    avg_ms = d["ms"] / d["n"]
-    if dom == 1:
-        # issued real MFMA work: 8 flops per complex MAC (4M) or 6 (3M)
-        issued = sum(o["flops"] * (0.75 if o.get("form") == 2 else 1.0) for o in ops if o["kind"] == 1)
-        achieved = issued / d["n"] / (avg_ms / 1e3) / 1e12
-        roof = {"kernel": KIND_NAMES[dom], "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                "launches_per_slice": d["n"], "avg_ms": avg_ms,
-                "flop_per_launch": issued / d["n"],
-                "complex_tflops": d["flops"] / d["n"] / (avg_ms / 1e3) / 1e12,
-                "note": "achieved counts issued real MFMA flops (6 per complex MAC in the 3M form, 8 in 4M)"}
-    else:
-        achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
-        roof = {"kernel": KIND_NAMES[dom], "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": None, "launches_per_slice": d["n"], "avg_ms": avg_ms,
-                "bytes_per_launch": d["bytes"] / d["n"]}
-    perm = by_kind.get(0)
-    kernel_split = {KIND_NAMES[k]: {"ms_per_slice": v["ms"], "launches": v["n"]} for k, v in by_kind.items()}
-    if perm and perm["ms"] > 0:
-        kernel_split["k_permute"]["GB/s"] = perm["bytes"] / (perm["ms"] / 1e3) / 1e9
-        kernel_split["k_permute"]["frac_hbm"] = kernel_split["k_permute"]["GB/s"] / PEAK_HBM
-    log(f"[bench] per-kernel: {json.dumps(kernel_split)}")
-    order = sorted(range(len(ops)), key=lambda i: -ms[i])
-    for i in order[:16]:
-        o = ops[i]
-        shape = (f"M={o['M']} N={o['N']} K={o['K']}" if o["kind"] == 1 else
-                 f"rank={o['rank']}" if o["kind"] == 0 else f"nM={o['nM']} nN={o['nN']} nK={o['nK']}")
-        rate = (f"{o['flops'] / (ms[i] / 1e3) / 1e12:.1f} TFLOP/s" if o["kind"] == 1 else
-                f"{o['bytes'] / (ms[i] / 1e3) / 1e9:.0f} GB/s")
-        log(f"[bench]   op {i:3d} {KIND_NAMES.get(o['kind'], o['kind']):10s} {ms[i]:9.3f} ms  {shape:28s} {rate}")
+    n_slices = 1 << len(w.sliced)
+    K, W = min(args.steps, n_slices - args.warmup), args.warmup
+    main_res = run_network(tnrcs, torch, w, args.dtype, args.form, K, W, graph=not args.no_graph)
+    by_kind, split = kernel_split(main_res, args.dtype)
+    roof = roofline(by_kind, args.dtype)
+    info = main_res["info"]
+    main_res["plan"].close()
+    del main_res["plan"]
+    torch.cuda.empty_cache()
 
     if args.copy_probe_gib > 0:
         n = int(args.copy_probe_gib * 2**30) // 8
@@ -174,46 +296,69 @@ def main():
         log(f"[bench] copy probe: {n * 8} bytes read and written")
         del src, dst
 
+    extra = {}
+    if not args.no_extra:
+        prec = {}
+        for dt in ("f16s", "bf16s"):
+            if dt == args.dtype:
+                continue
+            r = run_network(tnrcs, torch, w, dt, "auto", K, W, profile=(dt == "f16s"))
+            err = float(np.linalg.norm(r["amp"] - main_res["amp"]) / np.linalg.norm(main_res["amp"]))
+            prec[dt] = {"sec_per_slice": r["sec_per_slice"], "complex_tflops": r["tflops"],
+                        "time_ratio_vs_" + args.dtype: main_res["sec_per_slice"] / r["sec_per_slice"],
+                        "rel_err_vs_" + args.dtype: err, "flags": r["flags"]}
+            if "ops" in r:
+                bk, _ = kernel_split(r, dt)
+                prec[dt]["roofline"] = roofline(bk, dt)
+            log(f"[bench] {dt}: {main_res['sec_per_slice'] / r['sec_per_slice']:.2f}x faster than {args.dtype}, "
+                f"bunch relative error vs {args.dtype} over the {K} timed slices {err:.2e}")
+            r["plan"].close()
+            del r
+            torch.cuda.empty_cache()
+        extra["precision"] = prec
+        extra["kernels"] = micro(tnrcs, torch, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(w, args.cpu_sub_log2)
         log(f"[bench] oracle: {cpu['value']:.4f} TFLOP/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
 
+    sec = main_res["sec_per_slice"]
     out = {
         "metric": METRIC,
-        "value": tflops,
+        "value": main_res["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": sec_per_slice * 1e3,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {
             "workload": "rqc-53q-6x9m1-d14: 53 qubits (6x9 grid, 1 seeded-missing site), 14 cycles, "
                         "6 open qubits (64-amplitude bunch), per-slice tensors <= 2^32 entries",
-            "sec_per_slice": sec_per_slice,
-            "complex_tflops": tflops,
-            "frac_fp32_mfma_peak": tflops / PEAK_FP32_MFMA,
+            "sec_per_slice": sec,
+            "complex_tflops": main_res["tflops"],
+            "frac_mfma_peak": main_res["tflops"] / PEAK[args.dtype],
             "n_slices_total": n_slices,
-            "extrapolated_total_s": sec_per_slice * n_slices,
+            "extrapolated_total_s": sec * n_slices,
             "flops_per_slice": info["flops_per_slice"],
             "bytes_per_slice": info["bytes_per_slice"],
             "gemm_form": args.form,
             "graph": not args.no_graph,
             "kernels_per_slice": info["n_kernels"],
-            "kernel_split": kernel_split,
-            "numeric_flags": flags,
+            "kernel_split": split,
+            "numeric_flags": main_res["flags"],
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extra": extra,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

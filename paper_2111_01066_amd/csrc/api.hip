@@ -165,11 +165,12 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
     case kOpGemm:
       if (dt == TN_DTYPE_C64)
         HIP_TRY(launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, op.gemm.M, op.gemm.N, op.gemm.K, 1,
-                                op.gemm.form, s, op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k),
+                                op.gemm.form, s, op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.tile),
                 "gemm kernel");
       else
         HIP_TRY(launch_gemm_half(dt, a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s,
-                                 op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.out_scale, slot),
+                                 op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.out_scale, slot,
+                                 op.gemm.tile),
                 "half gemm kernel");
       break;
     case kOpSplitK:

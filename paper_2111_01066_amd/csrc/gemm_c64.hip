@@ -229,11 +229,14 @@ bool gemm_shape_ok(int64_t M, int64_t N, int64_t K) {
 }
 
 hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
-                           int64_t batch, int form, hipStream_t s, float2* work, int splits) {
+                           int64_t batch, int form, hipStream_t s, float2* work, int splits, int tile) {
   if (!gemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
   if (splits < 1) splits = 1;
-  const bool big = (M % 128 == 0) && (N % 128 == 0);
+  const bool fits128 = (M % 128 == 0) && (N % 128 == 0);
+  if (tile == 128 && !fits128) return hipErrorInvalidValue;
+  if (tile == 64 && splits > 1) return hipErrorInvalidValue;
+  const bool big = fits128 && tile != 64;
   if (splits > 1) {
     if (batch != 1 || !work || !big || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
     const int64_t kl = K / splits;
@@ -251,7 +254,7 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
   if (batch > 65535) return hipErrorInvalidValue;
   // short contractions are store-bound: the 64x64 kernel keeps more
   // workgroups in flight
-  if (big && K > 64) {
+  if (big && (K > 64 || tile == 128)) {
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * batch));
     if (form == TN_GEMM_3M)

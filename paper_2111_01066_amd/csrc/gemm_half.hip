@@ -227,10 +227,12 @@ bool hgemm_shape_ok(int64_t M, int64_t N, int64_t K) {
 
 template <int FORM, typename H, typename E>
 static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, const E* B, void* C, int64_t N, int64_t K,
-                           int64_t kl, int64_t sA, int64_t sB, int64_t sC, float scale, float* maxslot, int to_work) {
+                           int64_t kl, int64_t sA, int64_t sB, int64_t sC, float scale, float* maxslot, int to_work,
+                           int tile) {
   // short contractions are store-bound: 64x64 tiles keep more workgroups in
   // flight; otherwise 128x128 tiles with 32-deep K stages
-  if (kl <= 64 || (M % 128) || (N % 128)) {
+  const bool small = tile == 64 || (tile == 0 && kl <= 64) || (M % 128) || (N % 128);
+  if (small) {
     const int64_t Mt = M / 64, Nt = N / 64;
     const dim3 grid((unsigned)(Mt * Nt * z));
     if (kl % 32 == 0)
@@ -253,39 +255,40 @@ static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, cons
 
 template <typename H, typename E>
 static hipError_t hgemm_t(const E* A, const E* B, E* C, int64_t M, int64_t N, int64_t K, int64_t batch, int form,
-                          hipStream_t s, float2* work, int splits, float scale, float* maxslot) {
+                          hipStream_t s, float2* work, int splits, float scale, float* maxslot, int tile) {
   if (splits > 1) {
     const int64_t kl = K / splits;
     if (form == TN_GEMM_3M)
-      hgemm_dispatch<TN_GEMM_3M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1);
+      hgemm_dispatch<TN_GEMM_3M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile);
     else
-      hgemm_dispatch<TN_GEMM_4M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1);
+      hgemm_dispatch<TN_GEMM_4M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile);
     const int64_t n = M * N;
     hipLaunchKernelGGL(k_hsplit_sum<E>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
                        work, C, n, splits, scale, maxslot);
     return hipGetLastError();
   }
   if (form == TN_GEMM_3M)
-    hgemm_dispatch<TN_GEMM_3M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0);
+    hgemm_dispatch<TN_GEMM_3M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile);
   else
-    hgemm_dispatch<TN_GEMM_4M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0);
+    hgemm_dispatch<TN_GEMM_4M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                             int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
-                            float* maxslot) {
+                            float* maxslot, int tile) {
   if (!hgemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
+  if (tile == 128 && ((M % 128) || (N % 128))) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
   if (splits < 1) splits = 1;
   if (splits > 1 && (batch != 1 || !work || K % (16 * splits) != 0 || splits > 65535)) return hipErrorInvalidValue;
   if (batch > 65535) return hipErrorInvalidValue;
   if (dtype == TN_DTYPE_F16S)
     return hgemm_t<_Float16, cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, M, N, K, batch, form, s, work, splits,
-                                   out_scale, maxslot);
+                                   out_scale, maxslot, tile);
   if (dtype == TN_DTYPE_BF16S)
     return hgemm_t<__bf16, cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, M, N, K, batch, form, s, work,
-                                  splits, out_scale, maxslot);
+                                  splits, out_scale, maxslot, tile);
   return hipErrorInvalidValue;
 }
 

@@ -47,6 +47,8 @@ struct GemmOp {
   int32_t form = TN_GEMM_4M;
   int32_t split_k = 1;  // K split into this many partial products (summed in a second pass)
   float out_scale = 1.f;  // scaled storage: 2^-s applied before rounding
+  int32_t tile = 0;       // workgroup tile edge: 0 = chosen by shape, 64 or 128 (autotuner)
+  int32_t split_max = 1;  // split-K workspace capacity in slabs
 };
 
 // Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],

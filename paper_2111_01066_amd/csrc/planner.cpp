@@ -276,7 +276,8 @@ void make_json(PlanCore& P) {
       js << "]";
     } else if (op.kind == kOpGemm) {
       js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
-         << ",\"split_k\":" << op.gemm.split_k << ",\"s_out\":" << op.s_out << ",\"w\":";
+         << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"s_out\":" << op.s_out
+         << ",\"w\":";
       json_ref(js, op.w);
     } else {
       js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
@@ -642,6 +643,7 @@ int build_plan(PlanCore& P, std::string& err) {
           sp *= 2;
         if (sp > 1) {
           g.gemm.split_k = sp;
+          g.gemm.split_max = sp;
           Buf wb{((int64_t)sp << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
           fix.push_back({gi, 3, (int)bufs.size()});
           bufs.push_back(wb);
