@@ -251,6 +251,79 @@ def micro(tnrcs, torch, np):
     return out
 
 
+def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
+    """Config 5: the frozen uneven circuits whose order costs at most `cap`
+    flops over all slices, one 64-amplitude bunch each, scaled storage,
+    autotuned GEMMs, one shared arena.  Times every plan's slices launched
+    plan by plan (each plan replaying its own per-slice graph) against the
+    same work as one batch graph launch; the two must agree bitwise."""
+    from rqcgen.workloads import config5, config5_table
+    t = config5_table()
+    wl = config5(max_total_flops=cap, table=t)
+    t0 = time.perf_counter()
+    need = 0
+    for w in wl:
+        dry = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, dry_run=True, tune=True)
+        need = max(need, dry.info()["arena_bytes"])
+        dry.close()
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    plans = [tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, arena=arena, tune=True,
+                        tune_db=tune_db) for w in wl]
+    t_plan = time.perf_counter() - t0
+    infos = [p.info() for p in plans]
+    n_sl = [i["n_slices"] for i in infos]
+    flops = float(sum(i["flops_per_slice"] * i["n_slices"] for i in infos))
+    kernels = int(sum((i["n_kernels"] + 1) * i["n_slices"] for i in infos))
+    log(f"[bench] batch: {len(plans)} circuits of {len(t['S'])} (order cost <= {cap:.0e} flop), {sum(n_sl)} slices, "
+        f"{kernels} kernels, {flops:.3e} flop, arena {need / 2**30:.2f} GiB, planned+tuned+calibrated in {t_plan:.1f} s")
+    amps_seq = torch.zeros(len(plans), 64, dtype=torch.complex128, device="cuda")
+    amps_b = torch.zeros_like(amps_seq)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def sequential():
+        for i, p in enumerate(plans):
+            p.contract(0, n_sl[i], amps_seq[i])
+
+    sequential()  # captures each plan's per-slice graph
+    torch.cuda.synchronize()
+    amps_seq.zero_()
+    ev0.record(stream)
+    sequential()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_seq = ev0.elapsed_time(ev1) / 1e3
+    log(f"[bench] batch: plan-by-plan launches {t_seq:.3f} s ({flops / t_seq / 1e12:.1f} complex TFLOP/s)")
+    t0 = time.perf_counter()
+    b = tnrcs.Batch(plans, [(0, n) for n in n_sl], [amps_b[i] for i in range(len(plans))])
+    t_build = time.perf_counter() - t0
+    b.run()
+    torch.cuda.synchronize()
+    amps_b.zero_()
+    ev0.record(stream)
+    b.run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_b = ev0.elapsed_time(ev1) / 1e3
+    same = bool(torch.equal(amps_b, amps_seq))
+    flags = 0
+    for p in plans:
+        flags |= p.status()
+    log(f"[bench] batch: one graph launch {t_b:.3f} s ({flops / t_b / 1e12:.1f} complex TFLOP/s), graph built in "
+        f"{t_build:.2f} s, identical to plan-by-plan: {same}, flags {flags}")
+    b.close()
+    for p in plans:
+        p.close()
+    del arena
+    torch.cuda.empty_cache()
+    return {"circuits": len(plans), "of": int(len(t["S"])), "max_order_flops": cap, "dtype": dtype,
+            "slices": int(sum(n_sl)), "kernels": kernels, "flops": flops, "arena_bytes": int(need),
+            "plan_tune_calibrate_s": t_plan, "graph_build_s": t_build,
+            "plan_by_plan_s": t_seq, "plan_by_plan_complex_tflops": flops / t_seq / 1e12,
+            "one_graph_s": t_b, "one_graph_complex_tflops": flops / t_b / 1e12, "speedup": t_seq / t_b,
+            "bitwise_identical": same, "numeric_flags": flags}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +335,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the precision variants and microbenchmarks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sub-log2", type=int, default=28)
+    ap.add_argument("--batch-cap", type=float, default=1e14,
+                    help="config 5: keep the circuits whose frozen order costs at most this many flops")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched uneven workload")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM-counter calibration)")
     args = ap.parse_args()
@@ -275,6 +351,9 @@ def main():
     from paper_2111_01066_amd import tnrcs
     from rqcgen.workloads import config3
 
+    if args.batch_only:
+        print(json.dumps({"batch_uneven": batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")}), flush=True)
+        return
     w = config3()
     log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
     n_slices = 1 << len(w.sliced)
@@ -317,6 +396,7 @@ def main():
             torch.cuda.empty_cache()
         extra["precision"] = prec
         extra["kernels"] = micro(tnrcs, torch, np)
+        extra["batch_uneven"] = batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")
 
     cpu = None
     if not args.no_cpu_baseline:

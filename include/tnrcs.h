@@ -89,8 +89,18 @@ typedef struct {
   int32_t device;         /* HIP device ordinal */
   int32_t host_fold_log2; /* steps whose result has at most 2^host_fold_log2 entries and whose operands
                              are leaves or folded leaves are evaluated once on the host in FP64 */
-  int32_t reserved;
-  int64_t arena_bytes;    /* device memory budget for intermediates (0: 92% of free memory) */
+  int32_t tune;           /* 1: at tn_plan time, time every dense GEMM step's tile size (64 or 128)
+                             and K-split count on the device and keep the fastest (see below) */
+  int64_t arena_bytes;    /* arena == NULL: device memory budget for intermediates (0: 92% of free
+                             memory); arena != NULL: the size of that workspace in bytes */
+  void* arena;            /* NULL: the plan allocates and owns its intermediate arena.  Otherwise a
+                             caller-owned device workspace of arena_bytes bytes (256-byte aligned)
+                             used for every intermediate; several plans may share one workspace as
+                             long as their runs are ordered (one stream, or a batch below).  It must
+                             outlive the plan.  tn_plan fails with TN_E_MEM if it is too small. */
+  const char* tune_db;    /* with tune: a text file caching tuning results across processes (read
+                             at the first use of a path, new results appended); NULL: the results
+                             are kept for the life of the process only */
 } tn_plan_opts;
 
 /* Per-plan totals for one slice (flop convention: one complex multiply-add = 8 flops). */
@@ -124,7 +134,15 @@ typedef struct {
  * before the cross-slice sum.  Later slices reuse the shifts; each slice
  * checks every step's largest stored magnitude and raises TN_FLAG_OVERFLOW
  * (the format's maximum reached) or TN_FLAG_UNDERFLOW (a step's largest
- * magnitude fell below 2^-2), read with tn_plan_status. */
+ * magnitude fell below 2^-2), read with tn_plan_status.
+ *
+ * Tuning (opts->tune): for each distinct dense-GEMM shape of the plan
+ * (dtype, M, N, K, form) every valid tile size and K-split count is timed
+ * with HIP events on the plan's own buffers (the arena is zero-filled first)
+ * and the fastest kept; results are cached per process and, with tune_db, in
+ * a file.  The split count changes the summation order inside a GEMM, so two
+ * processes that tune differently may differ in the last bits; a shared
+ * tune_db file makes the choice reproducible. */
 void tn_plan_opts_default(tn_plan_opts* o);
 
 /* Plans the contraction (main text TNC section; Supplement Fig. S2 and the
@@ -148,6 +166,31 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps,
  * ids; splitting a range over several calls gives the identical sum.  A plan
  * must be used by one stream at a time.  TN_E_UNSUPPORTED for dry-run plans. */
 int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream);
+
+/* ---- batches of plans (many circuits in one launch) ---- */
+
+typedef struct tn_batch_s* tn_batch_t;
+
+/* Captures, once, one HIP graph that runs plans[0..n) one after the other:
+ * for plan i the slices ranges[2i] <= s < ranges[2i+1], accumulated (+=)
+ * into amps[i] (device complex128[2^n_open of plan i]) exactly as
+ * tn_contract_slices would (same kernels, same order, same sums).  Plans may
+ * be of different circuits, sizes and dtypes, and may share one arena
+ * workspace (opts.arena); the same plan may appear more than once.  The
+ * plans and amplitude buffers must outlive the batch, and a plan must not be
+ * run elsewhere while the batch runs.  Node count: the sum over plans of
+ * (slices x (kernels per slice)) plus one per plan. */
+int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, void* const* amps, tn_batch_t* out);
+
+/* Enqueues the batch's graph on `stream` (one graph launch).  Asynchronous. */
+int tn_batch_run(tn_batch_t b, void* stream);
+
+/* Releases the batch's graph (not the plans).  NULL is accepted. */
+int tn_batch_destroy(tn_batch_t b);
+
+/* One-shot form: tn_batch_create, tn_batch_run on `stream`, wait for the
+ * stream, tn_batch_destroy. */
+int tn_contract_batch(const tn_plan_t* plans, const int64_t* ranges, void* const* amps, int32_t n, void* stream);
 
 /* Copies the plan's statistics into *s. */
 int tn_plan_info(tn_plan_t p, tn_plan_stats* s);

@@ -13,6 +13,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "tune.h"
 
 using namespace tnrcs;
 
@@ -70,6 +71,7 @@ struct tn_plan_s {
   char* d_leaves = nullptr;
   char* d_bound = nullptr;
   char* d_arena = nullptr;
+  bool own_arena = true;  // false: the caller's workspace (opts.arena)
   BindDesc* d_binds = nullptr;
   Ctrl* d_ctrl = nullptr;
   float* d_maxslots = nullptr;
@@ -84,6 +86,15 @@ struct tn_plan_s {
   const char* ext_a = nullptr;
   const char* ext_b = nullptr;
   char* ext_c = nullptr;
+};
+
+struct tn_batch_s {
+  int device = 0;
+  int64_t nodes = 0;
+  std::vector<tn_plan_s*> plans;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 static char* resolve(const tn_plan_s* p, const TRef& r) {
@@ -251,6 +262,28 @@ static int calibrate(tn_plan_s* p) {
   return upload_scales(p);
 }
 
+// Autotuning: zero the arena, then time each dense GEMM step's variants on
+// its own buffers (shapes seen before are answered from the cache).
+static int tune_plan(tn_plan_s* p) {
+  PlanCore& P = p->core;
+  bool any = false;
+  for (const Op& op : P.ops) any |= op.kind == kOpGemm;
+  if (!any) return TN_OK;
+  if (P.arena_elems > 0) HIP_TRY(hipMemset(p->d_arena, 0, (size_t)P.arena_elems * p->eb), "clear arena");
+  HIP_TRY(hipDeviceSynchronize(), "tuner synchronize");
+  for (Op& op : P.ops) {
+    if (op.kind != kOpGemm) continue;
+    std::string err;
+    float* slot = op.max_slot >= 0 ? p->d_maxslots + op.max_slot : nullptr;
+    float2* w = op.gemm.split_max > 1 ? reinterpret_cast<float2*>(resolve(p, op.w)) : nullptr;
+    int rc = tune_gemm(P.opts.dtype, op.gemm, resolve(p, op.a), resolve(p, op.b), resolve(p, op.c), w, slot,
+                       P.opts.tune_db, err);
+    if (rc) return fail(rc, err);
+  }
+  make_json(P);
+  return TN_OK;
+}
+
 static void drop_graph(tn_plan_s* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
@@ -266,7 +299,7 @@ static void release(tn_plan_s* p) {
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   hipFree(p->d_leaves);
   hipFree(p->d_bound);
-  hipFree(p->d_arena);
+  if (p->own_arena) hipFree(p->d_arena);
   hipFree(p->d_binds);
   hipFree(p->d_ctrl);
   hipFree(p->d_maxslots);
@@ -360,8 +393,16 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) return bail(hip_fail(e, "hipMemGetInfo"));
-  const int64_t need = (P.arena_elems + P.leaves_elems + P.bound_elems) * (int64_t)p->eb;
-  const int64_t budget = o.arena_bytes > 0 ? o.arena_bytes : (int64_t)(0.92 * (double)free_b);
+  const bool ext_arena = o.arena != nullptr;
+  if (ext_arena) {
+    if ((reinterpret_cast<uintptr_t>(o.arena) & 255) != 0) return bail(fail(TN_E_ARG, "arena not 256-byte aligned"));
+    if (P.arena_elems * (int64_t)p->eb > o.arena_bytes)
+      return bail(fail(TN_E_MEM, "plan needs an arena of " + std::to_string(P.arena_elems * (int64_t)p->eb) +
+                                     " bytes, workspace has " + std::to_string(o.arena_bytes)));
+  }
+  const int64_t need = ((ext_arena ? 0 : P.arena_elems) + P.leaves_elems + P.bound_elems) * (int64_t)p->eb;
+  const int64_t budget =
+      (!ext_arena && o.arena_bytes > 0) ? o.arena_bytes : (int64_t)(0.92 * (double)free_b);
   if (need > budget)
     return bail(fail(TN_E_MEM, "plan needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget)));
   auto dmalloc = [&](void** ptr, int64_t bytes, const char* what) -> int {
@@ -372,12 +413,16 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   };
   if ((rc = dmalloc((void**)&p->d_leaves, P.leaves_elems * p->eb, "alloc leaves")) ||
       (rc = dmalloc((void**)&p->d_bound, P.bound_elems * p->eb, "alloc bound leaves")) ||
-      (rc = dmalloc((void**)&p->d_arena, P.arena_elems * p->eb, "alloc arena")) ||
+      (!ext_arena && (rc = dmalloc((void**)&p->d_arena, P.arena_elems * p->eb, "alloc arena"))) ||
       (rc = dmalloc((void**)&p->d_maxslots, (int64_t)std::max(P.n_slots, 1) * 4, "alloc records")) ||
       (rc = dmalloc((void**)&p->d_outscales, (int64_t)std::max(P.n_slots, 1) * 4, "alloc scales")) ||
       (rc = dmalloc((void**)&p->d_binds, (int64_t)P.binds.size() * (int64_t)sizeof(BindDesc), "alloc binds")) ||
       (rc = dmalloc((void**)&p->d_ctrl, sizeof(Ctrl), "alloc control")))
     return bail(rc);
+  if (ext_arena) {
+    p->d_arena = static_cast<char*>(o.arena);
+    p->own_arena = false;
+  }
   if ((rc = upload_leaves(p))) return bail(rc);
   if (!P.binds.empty()) {
     e = hipMemcpy(p->d_binds, P.binds.data(), P.binds.size() * sizeof(BindDesc), hipMemcpyHostToDevice);
@@ -387,6 +432,7 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   Ctrl zero{};
   e = hipMemcpy(p->d_ctrl, &zero, sizeof(Ctrl), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(e, "init control"));
+  if (o.tune && (rc = tune_plan(p))) return bail(rc);
   if ((rc = calibrate(p))) return bail(rc);
   e = hipMemcpy(p->d_ctrl, &zero, sizeof(Ctrl), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(hip_fail(e, "init control"));
@@ -414,6 +460,9 @@ int tn_pair_plan(int32_t rank_a, const int32_t* labels_a, int32_t rank_b, const 
   P.pair_a.assign(labels_a, labels_a + rank_a);
   P.pair_b.assign(labels_b, labels_b + rank_b);
   P.pair_out.assign(labels_c, labels_c + rank_c);
+  o.tune = 0;
+  o.arena = nullptr;
+  o.tune_db = nullptr;
   P.opts = o;
   std::string err;
   int rc = build_pair_plan(P, err);
@@ -511,6 +560,108 @@ int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, v
     }
   }
   return TN_OK;
+}
+
+int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, void* const* amps, tn_batch_t* out) {
+  if (!out) return fail(TN_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || (n > 0 && (!plans || !ranges || !amps))) return fail(TN_E_ARG, "bad batch lists");
+  int device = -1;
+  int64_t nodes = 0;
+  for (int i = 0; i < n; ++i) {
+    const tn_plan_s* p = plans[i];
+    const std::string at = "batch entry " + std::to_string(i) + ": ";
+    if (!p) return fail(TN_E_ARG, at + "plan is NULL");
+    if (p->core.pair_mode) return fail(TN_E_ARG, at + "pairwise plan");
+    if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, at + "dry-run plan has no device state");
+    if (device >= 0 && p->device != device) return fail(TN_E_ARG, at + "plans on different devices");
+    device = p->device;
+    const int64_t b = ranges[2 * i], e = ranges[2 * i + 1];
+    if (b < 0 || e < b || e > p->core.stats.n_slices)
+      return fail(TN_E_ARG, at + "slice range outside [0, " + std::to_string(p->core.stats.n_slices) + ")");
+    if (e > b && !amps[i]) return fail(TN_E_ARG, at + "amp is NULL");
+    nodes += (e - b) * (int64_t)(p->core.stats.n_kernels + 1);
+  }
+  tn_batch_s* b = new (std::nothrow) tn_batch_s();
+  if (!b) return fail(TN_E_MEM, "host allocation failed");
+  b->plans.assign(plans, plans + n);
+  b->device = device < 0 ? 0 : device;
+  b->nodes = nodes;
+  if (nodes == 0) {
+    *out = b;
+    return TN_OK;
+  }
+  auto bail = [&](int code) {
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    delete b;
+    return code;
+  };
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
+  if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return bail(hip_fail(e, "create capture stream"));
+  if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return bail(hip_fail(e, "begin capture"));
+  int rc = TN_OK;
+  for (int i = 0; i < n && rc == TN_OK; ++i) {
+    tn_plan_s* p = plans[i];
+    const int64_t s0 = ranges[2 * i], s1 = ranges[2 * i + 1];
+    if (s1 == s0) continue;
+    hipError_t e2 = launch_set_ctrl(p->d_ctrl, s0, amps[i], b->cap_stream);
+    if (e2 != hipSuccess) rc = hip_fail(e2, "control kernel");
+    for (int64_t sl = s0; sl < s1 && rc == TN_OK; ++sl) rc = enqueue_slice(p, b->cap_stream);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return bail(rc);
+  }
+  if (e != hipSuccess) return bail(hip_fail(e, "end capture"));
+  b->graph = g;
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    hipGraphDestroy(b->graph);
+    return bail(hip_fail(e, "instantiate batch graph"));
+  }
+  hipStreamDestroy(b->cap_stream);
+  b->cap_stream = nullptr;
+  *out = b;
+  return TN_OK;
+}
+
+int tn_batch_run(tn_batch_t b, void* stream) {
+  if (!b) return fail(TN_E_ARG, "batch is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  for (tn_plan_s* p : b->plans) {
+    p->last_stream = s;
+    p->ran = true;
+  }
+  if (!b->exec) return TN_OK;
+  HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+  HIP_TRY(hipGraphLaunch(b->exec, s), "batch graph launch");
+  return TN_OK;
+}
+
+int tn_batch_destroy(tn_batch_t b) {
+  if (!b) return TN_OK;
+  hipSetDevice(b->device);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
+  return TN_OK;
+}
+
+int tn_contract_batch(const tn_plan_t* plans, const int64_t* ranges, void* const* amps, int32_t n, void* stream) {
+  tn_batch_t b = nullptr;
+  int rc = tn_batch_create(plans, n, ranges, amps, &b);
+  if (rc) return rc;
+  rc = tn_batch_run(b, stream);
+  if (rc == TN_OK) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) rc = hip_fail(e, "batch synchronize");
+  }
+  tn_batch_destroy(b);
+  return rc;
 }
 
 int tn_plan_profile(tn_plan_t p, int64_t slice, void* amp, void* stream, float* op_ms, int32_t cap,

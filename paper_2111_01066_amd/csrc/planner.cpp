@@ -276,7 +276,7 @@ void make_json(PlanCore& P) {
       js << "]";
     } else if (op.kind == kOpGemm) {
       js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
-         << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"s_out\":" << op.s_out
+         << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"split_max\":" << op.gemm.split_max << ",\"s_out\":" << op.s_out
          << ",\"w\":";
       json_ref(js, op.w);
     } else {
@@ -641,10 +641,18 @@ int build_plan(PlanCore& P, std::string& err) {
         while (tiles * sp < 2048 && ((int64_t)1 << nK) / (sp * 2) >= 1024 && sp < 64 &&
                ((int64_t)sp * 2 << (nM + nN)) <= ((int64_t)1 << 28))
           sp *= 2;
-        if (sp > 1) {
-          g.gemm.split_k = sp;
-          g.gemm.split_max = sp;
-          Buf wb{((int64_t)sp << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
+        // with tuning, room for every split the tuner may try: slabs of at
+        // least 256 along K, at most 64 slabs, workspace <= 2^28 entries,
+        // and only while the output has fewer than 8192 64x64 tiles
+        int cap = sp;
+        if (P.opts.tune && ((int64_t)1 << (nM + nN - 12)) < 8192)
+          while (cap < 64 && ((int64_t)1 << nK) / (cap * 2) >= 256 &&
+                 ((int64_t)cap * 2 << (nM + nN)) <= ((int64_t)1 << 28))
+            cap *= 2;
+        g.gemm.split_k = sp;
+        g.gemm.split_max = cap;
+        if (cap > 1) {
+          Buf wb{((int64_t)cap << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
           fix.push_back({gi, 3, (int)bufs.size()});
           bufs.push_back(wb);
         }

@@ -1,0 +1,140 @@
+// GEMM autotuner: for one dense GEMM step, times every valid (tile edge,
+// K-split count) variant on the step's own device buffers and keeps the
+// fastest.  Results are cached per process by (dtype, M, N, K, form, split
+// capacity) and, when a database path is given, in a plain text file
+// ("tnrcs-gemm dtype M N K form cap tile split ms" per line).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "tune.h"
+
+namespace tnrcs {
+namespace {
+
+using Key = std::tuple<int, int64_t, int64_t, int64_t, int, int>;  // dtype, M, N, K, form, cap
+
+struct Choice {
+  int tile = 0;
+  int split = 1;
+  float ms = 0.f;
+};
+
+std::mutex g_mu;
+std::map<Key, Choice> g_cache;
+std::map<std::string, std::set<Key>> g_db_keys;  // keys present in each database file
+
+void load_db(const std::string& path) {
+  if (g_db_keys.count(path)) return;
+  std::set<Key>& have = g_db_keys[path];
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char tag[32];
+  int dt, form, cap, tile, split;
+  long long M, N, K;
+  float ms;
+  while (std::fscanf(f, "%31s %d %lld %lld %lld %d %d %d %d %f", tag, &dt, &M, &N, &K, &form, &cap, &tile, &split,
+                     &ms) == 10) {
+    if (std::string(tag) != "tnrcs-gemm") continue;
+    const Key k{dt, M, N, K, form, cap};
+    g_cache[k] = Choice{tile, split, ms};
+    have.insert(k);
+  }
+  std::fclose(f);
+}
+
+void append_db(const std::string& path, const Key& k, const Choice& c) {
+  if (!g_db_keys[path].insert(k).second) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "tnrcs-gemm %d %lld %lld %lld %d %d %d %d %.5f\n", std::get<0>(k), (long long)std::get<1>(k),
+               (long long)std::get<2>(k), (long long)std::get<3>(k), std::get<4>(k), std::get<5>(k), c.tile, c.split,
+               c.ms);
+  std::fclose(f);
+}
+
+}  // namespace
+
+int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float2* w, float* slot, const char* db,
+              std::string& err) {
+  const Key key{dtype, g.M, g.N, g.K, g.form, g.split_max};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (db) load_db(db);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      if (db) append_db(db, key, it->second);  // a shape tuned earlier in this process
+      g.tile = it->second.tile;
+      g.split_k = it->second.split;
+      return TN_OK;
+    }
+  }
+  const bool fits128 = g.M % 128 == 0 && g.N % 128 == 0;
+  std::vector<std::pair<int, int>> variants;  // (tile, split)
+  for (int sp = 1; sp <= std::max(g.split_max, 1); sp *= 2) {
+    if (sp > 1 && (!w || g.K % (16 * sp) != 0)) continue;
+    for (int tile : {64, 128}) {
+      if (tile == 128 && !fits128) continue;
+      if (dtype == TN_DTYPE_C64 && sp > 1 && tile == 64) continue;  // c64 slabs use the 128 kernel
+      variants.push_back({tile, sp});
+    }
+  }
+  auto launch = [&](int tile, int sp) -> hipError_t {
+    float2* work = sp > 1 ? w : nullptr;
+    if (dtype == TN_DTYPE_C64)
+      return launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, g.M, g.N, g.K, 1, g.form, nullptr, work,
+                             sp, tile);
+    return launch_gemm_half(dtype, a, b, c, g.M, g.N, g.K, 1, g.form, nullptr, work, sp, 1.f, slot, tile);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    err = "tuner: event create failed";
+    if (e0) hipEventDestroy(e0);
+    return TN_E_HIP;
+  }
+  Choice best;
+  best.ms = INFINITY;
+  int rc = TN_OK;
+  for (auto [tile, sp] : variants) {
+    float t1 = 0.f, tr = 0.f;
+    hipError_t e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = launch(tile, sp);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t1, e0, e1);
+    // repeat to about 2 ms of work (at most 20 runs)
+    const int reps = std::max(1, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(tile, sp);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&tr, e0, e1);
+    if (e != hipSuccess) {
+      err = std::string("tuner: ") + hipGetErrorString(e);
+      rc = TN_E_HIP;
+      break;
+    }
+    const float ms = tr / reps;
+    if (ms < best.ms) best = Choice{tile, sp, ms};
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (variants.empty()) return TN_OK;
+  g.tile = best.tile;
+  g.split_k = best.split;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key] = best;
+  if (db) append_db(db, key, best);
+  return TN_OK;
+}
+
+}  // namespace tnrcs

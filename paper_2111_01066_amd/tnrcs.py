@@ -57,7 +57,7 @@ class tn_circuit(ctypes.Structure):
 class tn_plan_opts(ctypes.Structure):
     _fields_ = [("dtype", c_int32), ("gemm_form", c_int32), ("max_log2", c_int32), ("use_graph", c_int32),
                 ("dry_run", c_int32), ("device", c_int32), ("host_fold_log2", c_int32),
-                ("reserved", c_int32), ("arena_bytes", c_int64)]
+                ("tune", c_int32), ("arena_bytes", c_int64), ("arena", c_void_p), ("tune_db", c_char_p)]
 
 
 class tn_plan_stats(ctypes.Structure):
@@ -91,12 +91,17 @@ _lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c
                                ctypes.c_float, c_void_p, c_int32, c_void_p, c_void_p]
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                               c_void_p, c_int32, c_void_p]
+_lib.tn_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_void_p), POINTER(c_void_p)]
+_lib.tn_batch_run.argtypes = [c_void_p, c_void_p]
+_lib.tn_batch_destroy.argtypes = [c_void_p]
+_lib.tn_contract_batch.argtypes = [POINTER(c_void_p), POINTER(c_int64), POINTER(c_void_p), c_int32, c_void_p]
 _lib.tn_amp_norm2.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_xeb.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_void_p, c_void_p]
 
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
+            "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
             "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
 
 
@@ -159,7 +164,10 @@ class Plan:
     def __init__(self, circuit, pairs: Sequence, sliced: Sequence[int] = (), open_qubits: Sequence[int] = (),
                  out_bits=None, dtype: str = "c64", gemm_form: str = "auto", dry_run: bool = False,
                  use_graph: bool = True, host_fold_log2: int = 12, device: int = 0, arena_bytes: int = 0,
-                 max_log2: int = 0):
+                 max_log2: int = 0, tune: bool = False, tune_db: Optional[str] = None, arena=None):
+        """arena: a caller-owned device workspace for the intermediates (a
+        torch tensor, or an int address with arena_bytes); it must outlive
+        the plan and may be shared by plans whose runs are ordered."""
         self._h = None
         c, keep = marshal_circuit(circuit, out_bits)
         flat = [int(x) for p in pairs for x in p]
@@ -172,6 +180,14 @@ class Plan:
         o.device = int(device)
         o.arena_bytes = int(arena_bytes)
         o.max_log2 = int(max_log2)
+        o.tune = int(tune)
+        db = tune_db.encode() if tune_db else None
+        o.tune_db = db
+        self._arena = arena
+        if arena is not None:
+            o.arena = _ptr(arena)
+            if not isinstance(arena, int):
+                o.arena_bytes = int(arena.numel() * arena.element_size())
         h = c_void_p()
         _check(_lib.tn_plan(byref(c), _i32(flat), len(pairs), _i32(sliced), len(sliced), _i32(open_qubits),
                             len(open_qubits), byref(o), byref(h)))
@@ -241,6 +257,46 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Owns a tn_batch_t: one captured HIP graph that runs plans[i] over the
+    slice range ranges[i] into amps[i], for all i, in list order."""
+
+    def __init__(self, plans: Sequence[Plan], ranges: Sequence, amps: Sequence):
+        self._h = None
+        n = len(plans)
+        if len(ranges) != n or len(amps) != n:
+            raise ValueError("plans, ranges and amps must have the same length")
+        self._plans = list(plans)      # keep the plans and buffers alive
+        self._amps = list(amps)
+        hp = (c_void_p * max(1, n))(*[p._h for p in plans])
+        rg = (c_int64 * max(1, 2 * n))(*[int(x) for r in ranges for x in r])
+        am = (c_void_p * max(1, n))(*[_ptr(a) for a in amps])
+        h = c_void_p()
+        _check(_lib.tn_batch_create(hp, n, rg, am, byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib.tn_batch_run(self._h, c_void_p(_stream(stream))))
+
+    def close(self):
+        if self._h is not None:
+            _check(_lib.tn_batch_destroy(self._h))
+            self._h = None
+
+    __del__ = Plan.__del__
+    __enter__ = Plan.__enter__
+    __exit__ = Plan.__exit__
+
+
+def tn_contract_batch(plans: Sequence[Plan], ranges: Sequence, amps: Sequence, stream=None):
+    """One-shot batch: capture, launch, wait, release."""
+    n = len(plans)
+    hp = (c_void_p * max(1, n))(*[p._h for p in plans])
+    rg = (c_int64 * max(1, 2 * n))(*[int(x) for r in ranges for x in r])
+    am = (c_void_p * max(1, n))(*[_ptr(a) for a in amps])
+    _check(_lib.tn_contract_batch(hp, rg, am, n, c_void_p(_stream(stream))))
 
 
 class PairPlan:

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs shared by the contraction library's callers and the
 CPU oracle: random circuits, the canonical network's wire structure, and a
 greedy contraction-order finder with index slicing.  No tensor arithmetic."""
-from .circuit import (Circuit, Gate, make_rqc, make_uneven_batch, random_bitstrings,
+from .circuit import (Circuit, Gate, make_rqc, make_uneven_batch, uneven_circuit, random_bitstrings,
                       bits_to_index, near_square_grid, one_qubit_matrix, fsim_matrix,
                       cycle_patterns, pattern_edges)
 from .network import NetworkStructure, network_structure

@@ -176,17 +176,20 @@ def near_square_grid(n: int) -> Tuple[int, int]:
     return rows, cols
 
 
+def uneven_circuit(i: int, seed0: int = 1000, n_range=(24, 40), d_range=(10, 20)) -> Circuit:
+    """Circuit i of the uneven batch: n and d drawn from seed0 + i, a
+    near-square grid with the surplus sites dropped by the same seed."""
+    rng = np.random.default_rng(seed0 + i)
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    d = int(rng.integers(d_range[0], d_range[1] + 1))
+    rows, cols = near_square_grid(n)
+    return make_rqc(rows, cols, d, seed0 + i, n_missing=rows * cols - n)
+
+
 def make_uneven_batch(count: int, seed0: int = 1000, n_range=(24, 40),
                       d_range=(10, 20)) -> List[Circuit]:
     """Circuits of uneven size: n and d drawn per circuit from seed0 + i."""
-    out = []
-    for i in range(count):
-        rng = np.random.default_rng(seed0 + i)
-        n = int(rng.integers(n_range[0], n_range[1] + 1))
-        d = int(rng.integers(d_range[0], d_range[1] + 1))
-        rows, cols = near_square_grid(n)
-        out.append(make_rqc(rows, cols, d, seed0 + i, n_missing=rows * cols - n))
-    return out
+    return [uneven_circuit(i, seed0, n_range, d_range) for i in range(count)]
 
 
 def random_bitstrings(n: int, count: int, seed: int) -> np.ndarray:

@@ -10,6 +10,11 @@ and contraction orders for the benchmark configurations.
   closed at uniformly random bits (seed 3); sliced so every per-slice tensor
   has at most 2^32 entries.  Its order is frozen in data/config3_order.json
   (written by make_orders.py) so every machine contracts the same network.
+* config 5: the batched uneven workload, 512 circuits from make_uneven_batch
+  (24..40 qubits, 10..20 cycles, seeds 1000 + i), the 6 highest-numbered
+  qubits of each open, the others closed at uniformly random bits (seed
+  1000 + i); orders and sliced wires frozen in data/config5_orders.npz
+  (written by make_batch_orders.py; at most 8 sliced wires each).
 """
 from __future__ import annotations
 
@@ -20,7 +25,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .circuit import Circuit, make_rqc, random_bitstrings
+from .circuit import Circuit, make_rqc, random_bitstrings, uneven_circuit
 from .network import network_structure
 from .order import greedy_order
 
@@ -83,3 +88,31 @@ def config2_pair(seed: int = 2):
     lb = list(rng.permutation(shared + free_b))
     lo = list(rng.permutation(free_a + free_b))
     return [int(x) for x in la], [int(x) for x in lb], [int(x) for x in lo]
+
+
+def config5_table() -> dict:
+    """The frozen per-circuit order table of config 5 (numpy arrays)."""
+    with np.load(os.path.join(DATA, "config5_orders.npz"), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def config5(indices=None, max_total_flops: float = None, table: dict = None) -> List[Workload]:
+    """Config-5 circuits (all 512, the given indices, or those whose frozen
+    order costs at most max_total_flops over all slices), in index order."""
+    t = table if table is not None else config5_table()
+    count = len(t["S"])
+    idx = range(count) if indices is None else indices
+    out = []
+    for i in idx:
+        if max_total_flops is not None and t["total_flops"][i] > max_total_flops:
+            continue
+        c = uneven_circuit(i)
+        open_q = list(range(c.n_qubits - 6, c.n_qubits))
+        bits = random_bitstrings(c.n_qubits, 1, seed=1000 + i)[0]
+        bits[open_q] = 0
+        p0, p1 = t["pair_off"][i], t["pair_off"][i + 1]
+        s0, s1 = t["sliced_off"][i], t["sliced_off"][i + 1]
+        pairs = [(int(a), int(b)) for a, b in t["pairs"][p0:p1]]
+        sliced = [int(x) for x in t["sliced"][s0:s1]]
+        out.append(Workload(f"uneven-{i}-{c.n_qubits}q-d{c.cycles}", c, open_q, bits, pairs, sliced))
+    return out

@@ -128,3 +128,40 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(tnrcs.EXPORTED)
+
+
+def test_batch_argument_checks_without_device():
+    c = make_rqc(3, 4, 8, seed=1)
+    ns = network_structure(c, [0])
+    pairs = greedy_order(ns, seed=0)
+    plan = tnrcs.Plan(c, pairs, [], [0], None, dry_run=True)
+    with pytest.raises(tnrcs.TnError) as e:
+        tnrcs.Batch([plan], [(0, 1)], [0])
+    assert e.value.code == -5
+    with pytest.raises(ValueError):
+        tnrcs.Batch([plan], [], [])
+    # an empty batch is valid and launches nothing
+    b = tnrcs.Batch([], [], [])
+    b.run(stream=0)
+    b.close()
+
+
+def test_tuning_reserves_split_workspace_in_the_plan():
+    c = make_rqc(4, 5, 12, seed=5)
+    open_q = list(range(20))
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, 24)
+    base = tnrcs.Plan(c, pairs, sliced, open_q, None, dry_run=True)
+    tuned = tnrcs.Plan(c, pairs, sliced, open_q, None, dry_run=True, tune=True)
+    g0 = [o for o in base.json()["ops"] if o["kind"] == 1]
+    g1 = [o for o in tuned.json()["ops"] if o["kind"] == 1]
+    assert len(g0) == len(g1) > 0
+    for a, b in zip(g0, g1):
+        assert (a["M"], a["N"], a["K"], a["split_k"]) == (b["M"], b["N"], b["K"], b["split_k"])
+        assert a["split_max"] == a["split_k"] or a["split_k"] == 1
+        assert b["split_max"] >= b["split_k"]
+        # split slabs stay at least 256 deep and the workspace at most 2^28 entries
+        if b["split_max"] > 1:
+            assert b["K"] // b["split_max"] >= 256 and b["split_max"] * b["M"] * b["N"] <= 2 ** 28
+    assert tuned.info()["arena_bytes"] >= base.info()["arena_bytes"]
