@@ -181,7 +181,7 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
       else
         HIP_TRY(launch_gemm_half(dt, a, b, c, op.gemm.M, op.gemm.N, op.gemm.K, 1, op.gemm.form, s,
                                  op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.out_scale, slot,
-                                 op.gemm.tile),
+                                 op.gemm.tile, op.gemm.occ),
                 "half gemm kernel");
       break;
     case kOpSplitK:

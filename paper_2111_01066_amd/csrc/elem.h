@@ -51,8 +51,7 @@ __device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
 // floats order like their bit patterns).  One atomic per workgroup at most,
 // and none once the record already holds a larger value.  Every thread of
 // the workgroup must call it.
-__device__ __forceinline__ void record_max(float* slot, float v) {
-  __shared__ float wmax[16];
+__device__ __forceinline__ void record_max_in(float* slot, float v, float* wmax) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if ((threadIdx.x & 63) == 0) wmax[w] = v;
@@ -64,6 +63,11 @@ __device__ __forceinline__ void record_max(float* slot, float v) {
     const unsigned int bits = __float_as_uint(m);
     if (bits > __atomic_load_n(u, __ATOMIC_RELAXED)) atomicMax(u, bits);
   }
+}
+
+__device__ __forceinline__ void record_max(float* slot, float v) {
+  __shared__ float wmax[16];
+  record_max_in(slot, v, wmax);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id.  This maps a

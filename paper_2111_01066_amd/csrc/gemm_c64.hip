@@ -98,17 +98,19 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
 
 // 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32 MFMA
 // tiles), K staged through LDS 16 at a time; the next K tile is loaded into
-// registers while the current one is multiplied.  Planar LDS: re, im (and,
-// for 3M, re+im formed once per element when the tile is stored).  blockIdx.z
-// selects a batch entry or a split-K slab through the strides sA, sB, sC.
+// registers while the current one is multiplied.  Planar LDS: re, im; the
+// 3M operand sums re+im are formed in registers after the LDS reads, which
+// keeps the kernel within 256 registers per lane (two waves per SIMD).
+// blockIdx.z selects a batch entry or a split-K slab through the strides sA,
+// sB, sC.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
+__global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
                                                  float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
                                                  int64_t sA, int64_t sB, int64_t sC, int64_t Mt, int64_t Nt) {
   constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
   constexpr int BM = 128, BN = 128, BK = 16, LD = BM + 2;
-  __shared__ float As[P][BK][LD];
-  __shared__ float Bs[P][BK][LD];
+  __shared__ float As[2][BK][LD];
+  __shared__ float Bs[2][BK][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t tm, tn, z;
   xcd_tile(blockIdx.x, Mt, Nt, gridDim.x, tm, tn, z);
@@ -146,12 +148,6 @@ __global__ __launch_bounds__(256) void k_cgemm128(const float2* __restrict__ A, 
       Bs[1][lk + 2 * j][lrow] = rb[j].y;
       Bs[0][lk + 2 * j + 1][lrow] = rb[j].z;
       Bs[1][lk + 2 * j + 1][lrow] = rb[j].w;
-      if (P == 3) {
-        As[P - 1][lk + 2 * j][lrow] = ra[j].x + ra[j].y;
-        As[P - 1][lk + 2 * j + 1][lrow] = ra[j].z + ra[j].w;
-        Bs[P - 1][lk + 2 * j][lrow] = rb[j].x + rb[j].y;
-        Bs[P - 1][lk + 2 * j + 1][lrow] = rb[j].z + rb[j].w;
-      }
     }
     __syncthreads();
     if (k0 + BK < k_len) {
@@ -166,11 +162,17 @@ __global__ __launch_bounds__(256) void k_cgemm128(const float2* __restrict__ A, 
       const int kr = kk + kh;
       float a[P][2], b[P][2];
 #pragma unroll
-      for (int p = 0; p < P; ++p)
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           a[p][i] = As[p][kr][wm + 32 * i + c];
           b[p][i] = Bs[p][kr][wn + 32 * i + c];
+        }
+      if (P == 3)  // 3M operand sums, formed in FP32 from the staged re/im
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[P - 1][i] = a[0][i] + a[1][i];
+          b[P - 1][i] = b[0][i] + b[1][i];
         }
 #pragma unroll
       for (int i = 0; i < 2; ++i)

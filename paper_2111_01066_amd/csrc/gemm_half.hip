@@ -73,8 +73,8 @@ __device__ __forceinline__ void store_stage(H (*S)[BM][LDK], const uint4* r, int
   }
 }
 
-template <int FORM, int BK, int WT, typename H, typename E>
-__global__ __launch_bounds__(256, 2) void k_hgemm128(const E* __restrict__ A, const E* __restrict__ B,
+template <int FORM, int BK, int WT, int OCC, typename H, typename E>
+__global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, const E* __restrict__ B,
                                                  void* __restrict__ Cout, int64_t N, int64_t K, int64_t k_len,
                                                  int64_t sA, int64_t sB, int64_t sC, float out_scale,
                                                  float* maxslot, int to_work, int64_t Mt, int64_t Nt) {
@@ -200,7 +200,9 @@ __global__ __launch_bounds__(256, 2) void k_hgemm128(const E* __restrict__ A, co
           reinterpret_cast<E*>(Cout)[z * sC + o] = from_f2<E>(re * out_scale, im * out_scale);
         }
       }
-  if (!to_work) record_max(maxslot, mx);
+  // the block reduction reuses the (now idle) stage buffers: no LDS beyond
+  // the two stages, so two workgroups fit in one CU's LDS
+  if (!to_work) record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
 }
 
 // C[i] = (sum over slabs s, in order, of W[s][i]) * scale, rounded to E.
@@ -228,7 +230,7 @@ bool hgemm_shape_ok(int64_t M, int64_t N, int64_t K) {
 template <int FORM, typename H, typename E>
 static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, const E* B, void* C, int64_t N, int64_t K,
                            int64_t kl, int64_t sA, int64_t sB, int64_t sC, float scale, float* maxslot, int to_work,
-                           int tile) {
+                           int tile, int occ) {
   // short contractions are store-bound: 64x64 tiles keep more workgroups in
   // flight; otherwise 128x128 tiles with 32-deep K stages
   const bool small = tile == 64 || (tile == 0 && kl <= 64) || (M % 128) || (N % 128);
@@ -236,47 +238,55 @@ static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, cons
     const int64_t Mt = M / 64, Nt = N / 64;
     const dim3 grid((unsigned)(Mt * Nt * z));
     if (kl % 32 == 0)
-      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
-                         maxslot, to_work, Mt, Nt);
+      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+                         scale, maxslot, to_work, Mt, Nt);
     else
-      hipLaunchKernelGGL((k_hgemm128<FORM, 16, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
-                         maxslot, to_work, Mt, Nt);
+      hipLaunchKernelGGL((k_hgemm128<FORM, 16, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+                         scale, maxslot, to_work, Mt, Nt);
     return;
   }
+  // two waves per SIMD (registers capped at 256) hide latency on short K;
+  // one wave per SIMD (no cap) pipelines long K better
+  if (occ == 0) occ = kl >= 16384 ? 1 : 2;
   const int64_t Mt = M / 128, Nt = N / 128;
   const dim3 grid((unsigned)(Mt * Nt * z));
-  if (kl % 32 == 0)
-    hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+  if (kl % 32 == 0) {
+    if (occ == 1)
+      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+                         scale, maxslot, to_work, Mt, Nt);
+    else
+      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+                         scale, maxslot, to_work, Mt, Nt);
+  } else {
+    hipLaunchKernelGGL((k_hgemm128<FORM, 16, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
                        maxslot, to_work, Mt, Nt);
-  else
-    hipLaunchKernelGGL((k_hgemm128<FORM, 16, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
-                       maxslot, to_work, Mt, Nt);
+  }
 }
 
 template <typename H, typename E>
 static hipError_t hgemm_t(const E* A, const E* B, E* C, int64_t M, int64_t N, int64_t K, int64_t batch, int form,
-                          hipStream_t s, float2* work, int splits, float scale, float* maxslot, int tile) {
+                          hipStream_t s, float2* work, int splits, float scale, float* maxslot, int tile, int occ) {
   if (splits > 1) {
     const int64_t kl = K / splits;
     if (form == TN_GEMM_3M)
-      hgemm_dispatch<TN_GEMM_3M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile);
+      hgemm_dispatch<TN_GEMM_3M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile, occ);
     else
-      hgemm_dispatch<TN_GEMM_4M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile);
+      hgemm_dispatch<TN_GEMM_4M, H, E>(M, splits, s, A, B, work, N, K, kl, kl, kl, M * N, 1.f, nullptr, 1, tile, occ);
     const int64_t n = M * N;
     hipLaunchKernelGGL(k_hsplit_sum<E>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
                        work, C, n, splits, scale, maxslot);
     return hipGetLastError();
   }
   if (form == TN_GEMM_3M)
-    hgemm_dispatch<TN_GEMM_3M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile);
+    hgemm_dispatch<TN_GEMM_3M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile, occ);
   else
-    hgemm_dispatch<TN_GEMM_4M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile);
+    hgemm_dispatch<TN_GEMM_4M, H, E>(M, batch, s, A, B, C, N, K, K, M * K, N * K, M * N, scale, maxslot, 0, tile, occ);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                             int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
-                            float* maxslot, int tile) {
+                            float* maxslot, int tile, int occ) {
   if (!hgemm_shape_ok(M, N, K) || batch < 0) return hipErrorInvalidValue;
   if (tile == 128 && ((M % 128) || (N % 128))) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
@@ -285,10 +295,10 @@ hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, in
   if (batch > 65535) return hipErrorInvalidValue;
   if (dtype == TN_DTYPE_F16S)
     return hgemm_t<_Float16, cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, M, N, K, batch, form, s, work, splits,
-                                   out_scale, maxslot, tile);
+                                   out_scale, maxslot, tile, occ);
   if (dtype == TN_DTYPE_BF16S)
     return hgemm_t<__bf16, cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, M, N, K, batch, form, s, work,
-                                  splits, out_scale, maxslot, tile);
+                                  splits, out_scale, maxslot, tile, occ);
   return hipErrorInvalidValue;
 }
 

@@ -49,6 +49,7 @@ struct GemmOp {
   float out_scale = 1.f;  // scaled storage: 2^-s applied before rounding
   int32_t tile = 0;       // workgroup tile edge: 0 = chosen by shape, 64 or 128 (autotuner)
   int32_t split_max = 1;  // split-K workspace capacity in slabs
+  int32_t occ = 0;        // FP16/BF16 128x128 kernel: waves per SIMD (0 = chosen by K, 1 or 2; autotuner)
 };
 
 // Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],

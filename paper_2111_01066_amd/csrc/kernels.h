@@ -28,9 +28,10 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
                            int64_t batch, int form, hipStream_t s, float2* work = nullptr, int splits = 1,
                            int tile = 0);
 // scaled FP16/BF16 GEMM on half MFMA; C = A B^T * out_scale; max |A B^T| recorded in *maxslot.
+// tile: 0 auto, 64 or 128; occ (128 tiles): 0 auto, 1 or 2 waves per SIMD.
 hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                             int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
-                            float* maxslot, int tile = 0);
+                            float* maxslot, int tile = 0, int occ = 0);
 hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
                           hipStream_t s);
 // skewed contraction with B and A's K offsets in LDS (nN <= 4, nK + nN <= kSkinnyMaxLog2)

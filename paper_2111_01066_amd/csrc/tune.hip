@@ -2,7 +2,8 @@
 // K-split count) variant on the step's own device buffers and keeps the
 // fastest.  Results are cached per process by (dtype, M, N, K, form, split
 // capacity) and, when a database path is given, in a plain text file
-// ("tnrcs-gemm dtype M N K form cap tile split ms" per line).
+// ("tnrcs-gemm dtype M N K form cap tile split occ ms" per line; occ is the
+// waves-per-SIMD variant of the FP16/BF16 128x128 kernel, 0 elsewhere).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,6 +26,7 @@ using Key = std::tuple<int, int64_t, int64_t, int64_t, int, int>;  // dtype, M, 
 struct Choice {
   int tile = 0;
   int split = 1;
+  int occ = 0;
   float ms = 0.f;
 };
 
@@ -38,14 +40,14 @@ void load_db(const std::string& path) {
   FILE* f = std::fopen(path.c_str(), "r");
   if (!f) return;
   char tag[32];
-  int dt, form, cap, tile, split;
+  int dt, form, cap, tile, split, occ;
   long long M, N, K;
   float ms;
-  while (std::fscanf(f, "%31s %d %lld %lld %lld %d %d %d %d %f", tag, &dt, &M, &N, &K, &form, &cap, &tile, &split,
-                     &ms) == 10) {
+  while (std::fscanf(f, "%31s %d %lld %lld %lld %d %d %d %d %d %f", tag, &dt, &M, &N, &K, &form, &cap, &tile, &split,
+                     &occ, &ms) == 11) {
     if (std::string(tag) != "tnrcs-gemm") continue;
     const Key k{dt, M, N, K, form, cap};
-    g_cache[k] = Choice{tile, split, ms};
+    g_cache[k] = Choice{tile, split, occ, ms};
     have.insert(k);
   }
   std::fclose(f);
@@ -55,9 +57,9 @@ void append_db(const std::string& path, const Key& k, const Choice& c) {
   if (!g_db_keys[path].insert(k).second) return;
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "tnrcs-gemm %d %lld %lld %lld %d %d %d %d %.5f\n", std::get<0>(k), (long long)std::get<1>(k),
+  std::fprintf(f, "tnrcs-gemm %d %lld %lld %lld %d %d %d %d %d %.5f\n", std::get<0>(k), (long long)std::get<1>(k),
                (long long)std::get<2>(k), (long long)std::get<3>(k), std::get<4>(k), std::get<5>(k), c.tile, c.split,
-               c.ms);
+               c.occ, c.ms);
   std::fclose(f);
 }
 
@@ -74,25 +76,35 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
       if (db) append_db(db, key, it->second);  // a shape tuned earlier in this process
       g.tile = it->second.tile;
       g.split_k = it->second.split;
+      g.occ = it->second.occ;
       return TN_OK;
     }
   }
   const bool fits128 = g.M % 128 == 0 && g.N % 128 == 0;
-  std::vector<std::pair<int, int>> variants;  // (tile, split)
+  struct V {
+    int tile, split, occ;
+  };
+  std::vector<V> variants;
   for (int sp = 1; sp <= std::max(g.split_max, 1); sp *= 2) {
     if (sp > 1 && (!w || g.K % (16 * sp) != 0)) continue;
     for (int tile : {64, 128}) {
       if (tile == 128 && !fits128) continue;
       if (dtype == TN_DTYPE_C64 && sp > 1 && tile == 64) continue;  // c64 slabs use the 128 kernel
-      variants.push_back({tile, sp});
+      if (dtype != TN_DTYPE_C64 && tile == 128) {
+        variants.push_back({tile, sp, 1});
+        variants.push_back({tile, sp, 2});
+      } else {
+        variants.push_back({tile, sp, 0});
+      }
     }
   }
-  auto launch = [&](int tile, int sp) -> hipError_t {
-    float2* work = sp > 1 ? w : nullptr;
+  auto launch = [&](const V& v) -> hipError_t {
+    float2* work = v.split > 1 ? w : nullptr;
     if (dtype == TN_DTYPE_C64)
       return launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, g.M, g.N, g.K, 1, g.form, nullptr, work,
-                             sp, tile);
-    return launch_gemm_half(dtype, a, b, c, g.M, g.N, g.K, 1, g.form, nullptr, work, sp, 1.f, slot, tile);
+                             v.split, v.tile);
+    return launch_gemm_half(dtype, a, b, c, g.M, g.N, g.K, 1, g.form, nullptr, work, v.split, 1.f, slot, v.tile,
+                            v.occ);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -103,17 +115,17 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
   Choice best;
   best.ms = INFINITY;
   int rc = TN_OK;
-  for (auto [tile, sp] : variants) {
+  for (const V& v : variants) {
     float t1 = 0.f, tr = 0.f;
     hipError_t e = hipEventRecord(e0, nullptr);
-    if (e == hipSuccess) e = launch(tile, sp);
+    if (e == hipSuccess) e = launch(v);
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t1, e0, e1);
     // repeat to about 2 ms of work (at most 20 runs)
     const int reps = std::max(1, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(tile, sp);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(v);
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&tr, e0, e1);
@@ -123,7 +135,7 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
       break;
     }
     const float ms = tr / reps;
-    if (ms < best.ms) best = Choice{tile, sp, ms};
+    if (ms < best.ms) best = Choice{v.tile, v.split, v.occ, ms};
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -131,6 +143,7 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
   if (variants.empty()) return TN_OK;
   g.tile = best.tile;
   g.split_k = best.split;
+  g.occ = best.occ;
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[key] = best;
   if (db) append_db(db, key, best);

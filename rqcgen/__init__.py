@@ -6,4 +6,4 @@ from .circuit import (Circuit, Gate, make_rqc, make_uneven_batch, uneven_circuit
                       cycle_patterns, pattern_edges)
 from .network import NetworkStructure, network_structure
 from .order import (greedy_order, slice_to_fit, order_stats, find_order, validate_order,
-                    step_masks, live_peak, Plan, OrderStats)
+                    step_masks, live_peak, Plan, OrderStats, schroedinger_order)

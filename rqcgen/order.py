@@ -450,3 +450,72 @@ def bisection_order(ns: NetworkStructure, seed: int = 0, lo: float = 0.4, hi: fl
     the simplification rule applied first."""
     rng = np.random.default_rng(seed)
     return _Bisect(ns, rng, lo, hi, leaf_size, use_kl).run()
+
+
+def schroedinger_order(circuit, open_qubits: Sequence[int] = ()) -> List[Tuple[int, int]]:
+    """Gate-by-gate (state-vector-like) SSA order over the canonical leaves:
+    each qubit's |0> vector and the single-qubit gates between two two-qubit
+    gates are first contracted into the next two-qubit gate (small steps),
+    then every such block is contracted into the running state in circuit
+    order; trailing single-qubit gates and the output vectors of closed
+    qubits follow, and disjoint components are joined last.  The state has
+    at most n indices, so this order suits networks with many open qubits,
+    where graph-partitioning orders are poor."""
+    n = circuit.n_qubits
+    m = len(circuit.gates)
+    open_set = set(int(q) for q in open_qubits)
+    closed = [q for q in range(n) if q not in open_set]
+    pairs: List[Tuple[int, int]] = []
+    next_id = n + m + len(closed)
+
+    def contract(a: int, b: int) -> int:
+        nonlocal next_id
+        pairs.append((a, b))
+        next_id += 1
+        return next_id - 1
+
+    pending: List[Optional[int]] = list(range(n))   # small tensor not yet in the state, per qubit
+    comp: Dict[int, int] = {}                         # qubit -> id of the state component holding it
+    members: Dict[int, List[int]] = {}                # component id -> its qubits
+
+    def merge_into_state(block: int, qubits: Sequence[int]):
+        cur = block
+        qs: List[int] = []
+        seen = set()
+        for q in qubits:
+            c = comp.get(q)
+            if c is not None and c not in seen:
+                seen.add(c)
+                cur = contract(c, cur)
+                qs += members.pop(c)
+        for q in qubits:
+            if q not in qs:
+                qs.append(q)
+        members[cur] = qs
+        for q in qs:
+            comp[q] = cur
+
+    for gi, g in enumerate(circuit.gates):
+        leaf = n + gi
+        if len(g.qubits) == 1:
+            q = g.qubits[0]
+            pending[q] = leaf if pending[q] is None else contract(pending[q], leaf)
+            continue
+        block = leaf
+        for q in g.qubits:
+            if pending[q] is not None:
+                block = contract(block, pending[q])
+                pending[q] = None
+        merge_into_state(block, list(g.qubits))
+    for j, q in enumerate(closed):
+        out_leaf = n + m + j
+        pending[q] = out_leaf if pending[q] is None else contract(pending[q], out_leaf)
+    for q in range(n):
+        if pending[q] is not None:
+            merge_into_state(pending[q], [q])
+            pending[q] = None
+    roots = list(members)
+    cur = roots[0]
+    for r in roots[1:]:
+        cur = contract(cur, r)
+    return pairs

@@ -90,6 +90,23 @@ def config2_pair(seed: int = 2):
     return [int(x) for x in la], [int(x) for x in lb], [int(x) for x in lo]
 
 
+def config4() -> Workload:
+    """The 30-qubit cross-check network of the precision study: a 5x6 grid,
+    14 cycles, seed 4, every qubit open (2^30 amplitudes), contracted in the
+    gate-by-gate order."""
+    from .order import schroedinger_order
+    c = make_rqc(5, 6, 14, seed=4)
+    open_q = list(range(30))
+    return Workload("rqc-30q-5x6-d14-all-open", c, open_q, np.zeros(30, dtype=np.uint8),
+                    schroedinger_order(c, open_q), [])
+
+
+def config4_uniform_indices(n_samples: int = 100_000) -> np.ndarray:
+    """The uniformly drawn basis indices of the 30-qubit cross-check
+    (numpy default_rng(6))."""
+    return np.random.default_rng(6).integers(0, 2 ** 30, size=n_samples, dtype=np.int64)
+
+
 def config5_table() -> dict:
     """The frozen per-circuit order table of config 5 (numpy arrays)."""
     with np.load(os.path.join(DATA, "config5_orders.npz"), allow_pickle=False) as z:

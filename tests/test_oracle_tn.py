@@ -127,3 +127,21 @@ def test_contract_entries_matches_pairwise():
                                      coords[:, :5])
     ref = np.einsum("abc,de->abcde", A[..., 0, 0], B[0, 0]).reshape(-1)
     np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("rows,cols,d,seed,open_q", [(2, 3, 6, 1, list(range(6))), (3, 3, 5, 2, [0, 4]),
+                                                     (2, 2, 4, 3, []), (3, 4, 8, 4, list(range(12)))])
+def test_gate_by_gate_order_is_a_full_tree_and_exact(rows, cols, d, seed, open_q):
+    """The gate-by-gate order (used for all-open networks) validates as a
+    full SSA tree and contracts to the state-vector bunch; its largest
+    intermediate has at most n + 4 indices."""
+    from rqcgen.order import schroedinger_order, validate_order, order_stats
+    c = make_rqc(rows, cols, d, seed=seed)
+    bits = random_bitstrings(c.n_qubits, 1, seed=9)[0]
+    ns = network_structure(c, open_q)
+    pairs = schroedinger_order(c, open_q)
+    validate_order(ns, pairs)
+    assert order_stats(ns, pairs, []).log2_max <= c.n_qubits + 4
+    leaves, ow = oracle.build_network(c, open_q, bits)
+    got = oracle.contract_network(leaves, pairs, ow, {}).reshape(-1)
+    np.testing.assert_allclose(got, oracle.amplitudes_sv(c, open_q, bits), rtol=0, atol=1e-12)
