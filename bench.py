@@ -251,6 +251,60 @@ def micro(tnrcs, torch, np):
     return out
 
 
+def crosscheck_30q(tnrcs, torch, np):
+    """Config 4 cross-check: the 30-qubit all-open network (2^30 amplitudes)
+    in every storage type against the stored FP64 state-vector samples:
+    normwise amplitude error on 1e4 ideal and 1e4 uniform samples, and the
+    cross-entropy estimate over 1e5 samples of each kind vs FP64."""
+    from rqcgen.workloads import config4, config4_uniform_indices
+    path = os.path.join(ROOT, "tests", "golden", "config4_30q.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    w = config4()
+    N = 2 ** 30
+    ideal = torch.from_numpy(g["ideal_idx"].astype(np.int64)).cuda()
+    uni = torch.from_numpy(config4_uniform_indices()).cuda()
+    n_amp, stride = g["ideal_amp"].size, int(g["ideal_amp_stride"])
+    out = {}
+    for dtype in ("c64", "f16s", "bf16s"):
+        plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype)
+        amp = torch.zeros(N, dtype=torch.complex128, device="cuda")
+        plan.contract(0, 1, amp)  # first run captures the graph
+        torch.cuda.synchronize()
+        amp.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.contract(0, 1, amp)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        flops = plan.info()["flops_per_slice"]
+        flags = plan.status()
+        plan.close()
+        r = {"sec": sec, "complex_tflops": flops / sec / 1e12, "flags": flags}
+        for name, idx, sub in (("ideal", ideal, ideal[::stride][:n_amp]), ("uniform", uni, uni[:n_amp])):
+            got = amp[sub].cpu().numpy()
+            ref = g[f"{name}_amp"]
+            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+            tnrcs.tn_amp_xeb(amp, N, idx, idx.numel(), acc)
+            s1, s2 = acc.cpu().numpy()
+            m = idx.numel()
+            f = N * s1 / m - 1.0
+            se = float(np.sqrt(max(N * N * s2 / m - (f + 1.0) ** 2, 0.0) / m))
+            r[name] = {"amp_rel_err": err, "xeb": f, "xeb_fp64": float(g[f"xeb_{name}"]),
+                       "abs_delta_xeb": abs(f - float(g[f"xeb_{name}"])), "xeb_stderr": se}
+        out[dtype] = r
+        log(f"[bench] 30q all-open {dtype}: {sec:.3f} s, amplitude error ideal {r['ideal']['amp_rel_err']:.2e} "
+            f"uniform {r['uniform']['amp_rel_err']:.2e}, XEB ideal {r['ideal']['xeb']:.5f} (FP64 "
+            f"{r['ideal']['xeb_fp64']:.5f}, s.e. {r['ideal']['xeb_stderr']:.5f}), uniform {r['uniform']['xeb']:.5f}")
+        del amp
+        torch.cuda.empty_cache()
+    return out
+
+
 def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
     """Config 5: the frozen uneven circuits whose order costs at most `cap`
     flops over all slices, one 64-amplitude bunch each, scaled storage,
@@ -338,6 +392,7 @@ def main():
     ap.add_argument("--batch-cap", type=float, default=1e14,
                     help="config 5: keep the circuits whose frozen order costs at most this many flops")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched uneven workload")
+    ap.add_argument("--crosscheck-only", action="store_true", help="run only the 30-qubit precision cross-check")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM-counter calibration)")
     args = ap.parse_args()
@@ -351,6 +406,9 @@ def main():
     from paper_2111_01066_amd import tnrcs
     from rqcgen.workloads import config3
 
+    if args.crosscheck_only:
+        print(json.dumps({"crosscheck_30q": crosscheck_30q(tnrcs, torch, np)}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch_uneven": batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")}), flush=True)
         return
@@ -397,6 +455,7 @@ def main():
         extra["precision"] = prec
         extra["kernels"] = micro(tnrcs, torch, np)
         extra["batch_uneven"] = batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")
+        extra["crosscheck_30q"] = crosscheck_30q(tnrcs, torch, np)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -62,6 +62,15 @@ uint16_t encode_small_float(double v, int mant_bits, int exp_bias, int exp_max_f
 uint16_t to_f16_bits(double v) { return encode_small_float(v, 10, 15, 31); }
 uint16_t to_bf16_bits(double v) { return encode_small_float(v, 7, 127, 255); }
 
+// Value of a finite binary16 / bfloat16 encoding.
+double decode_small_float(uint16_t b, int mant_bits, int exp_bias) {
+  const int ef = (b & 0x7FFF) >> mant_bits;
+  const double m = (double)(b & ((1u << mant_bits) - 1u));
+  const double a = ef == 0 ? std::ldexp(m, 1 - exp_bias - mant_bits)
+                           : std::ldexp(1.0 + std::ldexp(m, -mant_bits), ef - exp_bias);
+  return (b & 0x8000u) ? -a : a;
+}
+
 }  // namespace
 
 struct tn_plan_s {
@@ -76,6 +85,7 @@ struct tn_plan_s {
   Ctrl* d_ctrl = nullptr;
   float* d_maxslots = nullptr;
   float* d_outscales = nullptr;
+  double2* d_kappa = nullptr;  // scaled storage: per sub-block rounding factors of the sliced leaves
   int64_t bind_max = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -131,21 +141,64 @@ static int upload_leaves(tn_plan_s* p) {
     h64.assign((size_t)P.leaves_elems, make_float2(0.f, 0.f));
   else
     h32.assign((size_t)P.leaves_elems, 0u);
-  for (const DevLeaf& d : P.dev_leaves)
-    for (size_t i = 0; i < d.data.size(); ++i) {
-      const double re = d.data[i].real(), im = d.data[i].imag();
-      if (dt == TN_DTYPE_C64) {
-        h64[d.stored_off + i] = make_float2((float)re, (float)im);
-      } else {
-        const double sc = std::ldexp(1.0, -d.e);
-        uint16_t r = dt == TN_DTYPE_F16S ? to_f16_bits(re * sc) : to_bf16_bits(re * sc);
-        uint16_t m = dt == TN_DTYPE_F16S ? to_f16_bits(im * sc) : to_bf16_bits(im * sc);
-        h32[d.stored_off + i] = (uint32_t)r | ((uint32_t)m << 16);
-      }
+  const bool f16 = dt == TN_DTYPE_F16S;
+  const int mant = f16 ? 10 : 7, bias = f16 ? 15 : 127;
+  std::complex<double> kappa0 = 1.0;
+  std::vector<std::complex<double>> kappa;  // sliced leaves' sub-block factors, in bind order
+  for (const DevLeaf& d : P.dev_leaves) {
+    if (dt == TN_DTYPE_C64) {
+      for (size_t i = 0; i < d.data.size(); ++i)
+        h64[d.stored_off + i] = make_float2((float)d.data[i].real(), (float)d.data[i].imag());
+      continue;
     }
+    // Round to nearest even, then measure what rounding did to the leaf as
+    // a whole.  Write round(L) = rho L + D with D orthogonal to L, per
+    // sub-block that one slice uses (rho = <L, round(L)> / <L, L>).  The
+    // amplitude is linear in every leaf, so the rho part scales it exactly by
+    // rho; the same gate tensors recur throughout a circuit, so these
+    // factors do not average out but compound with depth (a bias of the
+    // amplitudes' magnitude, visible in the cross-entropy estimate).  The
+    // accumulation divides them out in FP64; only D, which averages out,
+    // remains.
+    const double sc = std::ldexp(1.0, -d.e);
+    const size_t nb = d.data.size() >> d.n_sliced;
+    for (size_t blk = 0; blk < ((size_t)1 << d.n_sliced); ++blk) {
+      std::complex<double> dot = 0;
+      double ssq = 0;
+      for (size_t i = blk * nb; i < (blk + 1) * nb; ++i) {
+        const double re = d.data[i].real() * sc, im = d.data[i].imag() * sc;
+        const uint16_t r = f16 ? to_f16_bits(re) : to_bf16_bits(re);
+        const uint16_t m = f16 ? to_f16_bits(im) : to_bf16_bits(im);
+        h32[d.stored_off + i] = (uint32_t)r | ((uint32_t)m << 16);
+        const std::complex<double> x(re, im), xr(decode_small_float(r, mant, bias), decode_small_float(m, mant, bias));
+        dot += std::conj(x) * xr;
+        ssq += std::norm(x);
+      }
+      const std::complex<double> kap = (ssq > 0 && std::abs(dot) > 0) ? ssq / dot : std::complex<double>(1.0);
+      if (d.n_sliced == 0)
+        kappa0 *= kap;
+      else
+        kappa.push_back(kap);
+    }
+  }
   const void* src = dt == TN_DTYPE_C64 ? (const void*)h64.data() : (const void*)h32.data();
   if (P.leaves_elems > 0)
     HIP_TRY(hipMemcpy(p->d_leaves, src, (size_t)P.leaves_elems * p->eb, hipMemcpyHostToDevice), "upload leaves");
+  P.accum.kappa0_re = kappa0.real();
+  P.accum.kappa0_im = kappa0.imag();
+  if (dt != TN_DTYPE_C64 && !kappa.empty()) {
+    int64_t off = 0;
+    size_t j = 0;
+    for (const DevLeaf& d : P.dev_leaves)
+      if (d.n_sliced > 0) {
+        P.binds[j++].kappa_off = off;
+        off += (int64_t)1 << d.n_sliced;
+      }
+    if (!p->d_kappa)
+      HIP_TRY(hipMalloc((void**)&p->d_kappa, kappa.size() * sizeof(double2)), "alloc rounding factors");
+    HIP_TRY(hipMemcpy(p->d_kappa, kappa.data(), kappa.size() * sizeof(double2), hipMemcpyHostToDevice),
+            "upload rounding factors");
+  }
   return TN_OK;
 }
 
@@ -200,7 +253,8 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
 static int launch_bind_slice(tn_plan_s* p, hipStream_t s) {
   const PlanCore& P = p->core;
   if (!P.binds.empty())
-    HIP_TRY(launch_bind(p->eb, p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl, s),
+    HIP_TRY(launch_bind(p->eb, p->d_leaves, p->d_bound, p->d_binds, (int)P.binds.size(), p->bind_max, p->d_ctrl,
+                        p->d_kappa, s),
             "bind kernel");
   return TN_OK;
 }
@@ -208,7 +262,7 @@ static int launch_bind_slice(tn_plan_s* p, hipStream_t s) {
 static int launch_accum_slice(tn_plan_s* p, hipStream_t s) {
   const PlanCore& P = p->core;
   HIP_TRY(launch_accum(P.opts.dtype, resolve(p, P.accum.root), P.accum, p->d_ctrl, p->d_maxslots, p->d_outscales,
-                       P.n_slots, s),
+                       P.n_slots, p->d_kappa != nullptr, s),
           "accumulate kernel");
   return TN_OK;
 }
@@ -304,6 +358,7 @@ static void release(tn_plan_s* p) {
   hipFree(p->d_ctrl);
   hipFree(p->d_maxslots);
   hipFree(p->d_outscales);
+  if (p->d_kappa) hipFree(p->d_kappa);
 }
 
 extern "C" {

@@ -73,17 +73,17 @@ __device__ __forceinline__ void store_stage(H (*S)[BM][LDK], const uint4* r, int
   }
 }
 
-template <int FORM, int BK, int WT, int OCC, typename H, typename E>
-__global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, const E* __restrict__ B,
+template <int FORM, int BK, int WTM, int WTN, int OCC, typename H, typename E>
+__global__ __launch_bounds__(256, OCC) void k_hgemm(const E* __restrict__ A, const E* __restrict__ B,
                                                  void* __restrict__ Cout, int64_t N, int64_t K, int64_t k_len,
                                                  int64_t sA, int64_t sB, int64_t sC, float out_scale,
                                                  float* maxslot, int to_work, int64_t Mt, int64_t Nt) {
   typedef typename Frag<H>::T F;
   constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
-  constexpr int BM = 64 * WT, BN = 64 * WT, LDK = BK + 8;
-  constexpr int TPR = 256 / BM;  // threads per operand row
-  constexpr int CPT = BK / TPR;  // complex elements per thread per operand per stage
-  constexpr int NV = CPT / 4;    // uint4 loads per thread per operand
+  constexpr int BM = 64 * WTM, BN = 64 * WTN, LDK = BK + 8;
+  constexpr int TPRA = 256 / BM, TPRB = 256 / BN;  // threads per operand row
+  constexpr int NVA = BK / TPRA / 4;  // uint4 (4 complex) loads per thread per stage, A
+  constexpr int NVB = BK / TPRB / 4;  // same for B
   // two LDS buffers: the MFMAs read one stage while the next is stored
   __shared__ __attribute__((aligned(16))) H As[2][P][BM][LDK];
   __shared__ __attribute__((aligned(16))) H Bs[2][P][BN][LDK];
@@ -93,31 +93,30 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, 
   const int64_t bm = tm * BM, bn = tn * BN;
   A += z * sA;
   B += z * sB;
-  const int wm = (wave & 1) * 32 * WT, wn = (wave >> 1) * 32 * WT;
-  floatx16 acc[P][WT][WT];
+  const int wm = (wave & 1) * 32 * WTM, wn = (wave >> 1) * 32 * WTN;
+  floatx16 acc[P][WTM][WTN];
 #pragma unroll
   for (int p = 0; p < P; ++p)
 #pragma unroll
-    for (int i = 0; i < WT; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
-      for (int j = 0; j < WT; ++j) acc[p][i][j] = floatx16{};
-  const int lrow = tid / TPR, lk = (tid % TPR) * CPT;
-  const uint4* Ap = reinterpret_cast<const uint4*>(A + (bm + lrow) * K + lk);
-  const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + lrow) * K + lk);
-  uint4 ra[NV], rb[NV];
+      for (int j = 0; j < WTN; ++j) acc[p][i][j] = floatx16{};
+  const int arow = tid / TPRA, ak = (tid % TPRA) * (BK / TPRA);
+  const int brow = tid / TPRB, bk = (tid % TPRB) * (BK / TPRB);
+  const uint4* Ap = reinterpret_cast<const uint4*>(A + (bm + arow) * K + ak);
+  const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + brow) * K + bk);
+  uint4 ra[NVA], rb[NVB];
 #pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    ra[j] = Ap[j];
-    rb[j] = Bp[j];
-  }
-  store_stage<P, BM, LDK, NV, H>(As[0], ra, lrow, lk);
-  store_stage<P, BN, LDK, NV, H>(Bs[0], rb, lrow, lk);
+  for (int j = 0; j < NVA; ++j) ra[j] = Ap[j];
+#pragma unroll
+  for (int j = 0; j < NVB; ++j) rb[j] = Bp[j];
+  store_stage<P, BM, LDK, NVA, H>(As[0], ra, arow, ak);
+  store_stage<P, BN, LDK, NVB, H>(Bs[0], rb, brow, bk);
   if (BK < k_len) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      ra[j] = Ap[BK / 4 + j];
-      rb[j] = Bp[BK / 4 + j];
-    }
+    for (int j = 0; j < NVA; ++j) ra[j] = Ap[BK / 4 + j];
+#pragma unroll
+    for (int j = 0; j < NVB; ++j) rb[j] = Bp[BK / 4 + j];
   }
   __syncthreads();
   const int c = lane & 31, kq = (lane >> 5) * 8;
@@ -125,34 +124,43 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, 
   for (int64_t k0 = 0; k0 < k_len; k0 += BK) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
-      F a[P][WT], b[P][WT];
+      F a[P][WTM], b[P][WTN];
 #pragma unroll
-      for (int p = 0; p < P; ++p)
+      for (int p = 0; p < P; ++p) {
 #pragma unroll
-        for (int i = 0; i < WT; ++i) {
-          a[p][i] = *reinterpret_cast<const F*>(&As[cur][p][wm + 32 * i + c][kk + kq]);
-          b[p][i] = *reinterpret_cast<const F*>(&Bs[cur][p][wn + 32 * i + c][kk + kq]);
-        }
+        for (int i = 0; i < WTM; ++i) a[p][i] = *reinterpret_cast<const F*>(&As[cur][p][wm + 32 * i + c][kk + kq]);
 #pragma unroll
-      for (int i = 0; i < WT; ++i) {
-        F na;
-        if (FORM != TN_GEMM_3M) {
+        for (int j = 0; j < WTN; ++j) b[p][j] = *reinterpret_cast<const F*>(&Bs[cur][p][wn + 32 * j + c][kk + kq]);
+      }
+      if (FORM == TN_GEMM_3M) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+            acc[1][i][j] = Frag<H>::mfma(a[1][i], b[1][j], acc[1][i][j]);
+            acc[P - 1][i][j] = Frag<H>::mfma(a[P - 1][i], b[P - 1][j], acc[P - 1][i][j]);
+          }
+      } else {
+        // two passes over the (i, j) blocks, so that the two products
+        // accumulated into one register block are 2*WTM*WTN MFMAs apart
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+            acc[1][i][j] = Frag<H>::mfma(a[0][i], b[1][j], acc[1][i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
           uint4 t = __builtin_bit_cast(uint4, a[1][i]);
           t.x ^= 0x80008000u;
           t.y ^= 0x80008000u;
           t.z ^= 0x80008000u;
           t.w ^= 0x80008000u;
-          na = __builtin_bit_cast(F, t);
-        }
+          const F na = __builtin_bit_cast(F, t);
 #pragma unroll
-        for (int j = 0; j < WT; ++j) {
-          if (FORM == TN_GEMM_3M) {
-            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
-            acc[1][i][j] = Frag<H>::mfma(a[1][i], b[1][j], acc[1][i][j]);
-            acc[P - 1][i][j] = Frag<H>::mfma(a[P - 1][i], b[P - 1][j], acc[P - 1][i][j]);
-          } else {
-            acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
-            acc[1][i][j] = Frag<H>::mfma(a[0][i], b[1][j], acc[1][i][j]);
+          for (int j = 0; j < WTN; ++j) {
             acc[0][i][j] = Frag<H>::mfma(na, b[1][j], acc[0][i][j]);
             acc[1][i][j] = Frag<H>::mfma(a[1][i], b[0][j], acc[1][i][j]);
           }
@@ -160,15 +168,14 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, 
       }
     }
     if (k0 + BK < k_len) {
-      store_stage<P, BM, LDK, NV, H>(As[cur ^ 1], ra, lrow, lk);
-      store_stage<P, BN, LDK, NV, H>(Bs[cur ^ 1], rb, lrow, lk);
+      store_stage<P, BM, LDK, NVA, H>(As[cur ^ 1], ra, arow, ak);
+      store_stage<P, BN, LDK, NVB, H>(Bs[cur ^ 1], rb, brow, bk);
       if (k0 + 2 * BK < k_len) {
         const int64_t adv = (k0 + 2 * BK) / 4;  // uint4 = 4 complex elements
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          ra[j] = Ap[adv + j];
-          rb[j] = Bp[adv + j];
-        }
+        for (int j = 0; j < NVA; ++j) ra[j] = Ap[adv + j];
+#pragma unroll
+        for (int j = 0; j < NVB; ++j) rb[j] = Bp[adv + j];
       }
     }
     __syncthreads();
@@ -177,9 +184,9 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm128(const E* __restrict__ A, 
   float mx = 0.f;
   const int kh = lane >> 5;
 #pragma unroll
-  for (int i = 0; i < WT; ++i)
+  for (int i = 0; i < WTM; ++i)
 #pragma unroll
-    for (int j = 0; j < WT; ++j)
+    for (int j = 0; j < WTN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -238,10 +245,10 @@ static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, cons
     const int64_t Mt = M / 64, Nt = N / 64;
     const dim3 grid((unsigned)(Mt * Nt * z));
     if (kl % 32 == 0)
-      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+      hipLaunchKernelGGL((k_hgemm<FORM, 32, 1, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
                          scale, maxslot, to_work, Mt, Nt);
     else
-      hipLaunchKernelGGL((k_hgemm128<FORM, 16, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+      hipLaunchKernelGGL((k_hgemm<FORM, 16, 1, 1, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
                          scale, maxslot, to_work, Mt, Nt);
     return;
   }
@@ -252,13 +259,13 @@ static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, cons
   const dim3 grid((unsigned)(Mt * Nt * z));
   if (kl % 32 == 0) {
     if (occ == 1)
-      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+      hipLaunchKernelGGL((k_hgemm<FORM, 32, 2, 2, 1, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
                          scale, maxslot, to_work, Mt, Nt);
     else
-      hipLaunchKernelGGL((k_hgemm128<FORM, 32, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
+      hipLaunchKernelGGL((k_hgemm<FORM, 32, 2, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC,
                          scale, maxslot, to_work, Mt, Nt);
   } else {
-    hipLaunchKernelGGL((k_hgemm128<FORM, 16, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
+    hipLaunchKernelGGL((k_hgemm<FORM, 16, 2, 2, 2, H, E>), grid, dim3(256), 0, s, A, B, C, N, K, kl, sA, sB, sC, scale,
                        maxslot, to_work, Mt, Nt);
   }
 }

@@ -99,6 +99,7 @@ struct BindDesc {  // device-side descriptor of one sliced leaf
   int32_t n_sl;
   int32_t sbit[8];
   int32_t pos[8];
+  int64_t kappa_off;  // scaled storage: first entry of this leaf's rounding factors (one per sub-block)
 };
 
 struct AccumDesc {
@@ -107,6 +108,8 @@ struct AccumDesc {
   TRef root;
   int32_t root_ssa = -1;
   double root_scale = 1.0;  // 2^e_root for scaled storage
+  // scaled storage: product over the unsliced device leaves of <L, L>/<L, round(L)>
+  double kappa0_re = 1.0, kappa0_im = 0.0;
 };
 
 struct HostTensor {

@@ -13,13 +13,16 @@ struct Ctrl {
   double* amp;      // caller's complex128 accumulator (re, im pairs)
   uint32_t flags;   // TN_FLAG_* (sticky)
   uint32_t pad;
+  double kap_re, kap_im;  // scaled storage: product of the sliced leaves' rounding factors for this slice
 };
 
 inline int elem_bytes_of(int dtype) { return dtype == TN_DTYPE_C64 ? 8 : 4; }
 
 hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s);
+// Copies every sliced leaf's sub-block of the current slice; with kappa
+// (scaled storage) also stores the product of their rounding factors in ctrl.
 hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,
-                       int64_t max_elems, const Ctrl* ctrl, hipStream_t s);
+                       int64_t max_elems, Ctrl* ctrl, const double2* kappa, hipStream_t s);
 hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, const int32_t* perm, int64_t batch,
                           hipStream_t s);
 // complex64 GEMM on FP32 MFMA; splits > 1: K split into slabs summed in order
@@ -40,8 +43,10 @@ hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s);
 int64_t splitk_blocks(const IndexOp& op);
+// The slice result is multiplied by d.root_scale, d.kappa0 and, if
+// sliced_factors, by the per-slice factor that the bind kernel left in ctrl.
 hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,
-                        const float* out_scales, int n_slots, hipStream_t s);
+                        const float* out_scales, int n_slots, bool sliced_factors, hipStream_t s);
 hipError_t launch_norm2(const double* amp, int64_t n, double* out, hipStream_t s);
 hipError_t launch_xeb(const double* amp, int64_t n, const int64_t* idx, int64_t n_idx, double* out,
                       hipStream_t s);

@@ -38,9 +38,25 @@ hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s)
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_bind(const E* __restrict__ leaves, E* __restrict__ bound,
-                                              const BindDesc* __restrict__ descs, const Ctrl* __restrict__ ctrl) {
+                                              const BindDesc* __restrict__ descs, Ctrl* ctrl, int n_desc,
+                                              const double2* __restrict__ kappa) {
   const BindDesc& d = descs[blockIdx.y];
   const int64_t s = ctrl->cursor;
+  if (kappa && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    // product over the sliced leaves of the factor of the sub-block this slice uses
+    double kr = 1.0, ki = 0.0;
+    for (int i = 0; i < n_desc; ++i) {
+      const BindDesc& di = descs[i];
+      int64_t b = 0;
+      for (int j = 0; j < di.n_sl; ++j) b |= ((s >> di.sbit[j]) & 1ll) << (di.n_sl - 1 - j);
+      const double2 f = kappa[di.kappa_off + b];
+      const double t = kr * f.x - ki * f.y;
+      ki = kr * f.y + ki * f.x;
+      kr = t;
+    }
+    ctrl->kap_re = kr;
+    ctrl->kap_im = ki;
+  }
   int64_t off = 0;
   for (int i = 0; i < d.n_sl; ++i) off |= ((s >> d.sbit[i]) & 1ll) << d.pos[i];
   const E* src = leaves + d.src_off + off;
@@ -51,15 +67,16 @@ __global__ __launch_bounds__(256) void k_bind(const E* __restrict__ leaves, E* _
 }
 
 hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,
-                       int64_t max_elems, const Ctrl* ctrl, hipStream_t s) {
+                       int64_t max_elems, Ctrl* ctrl, const double2* kappa, hipStream_t s) {
   if (n_desc <= 0) return hipSuccess;
   const int64_t gx = std::max<int64_t>(std::min<int64_t>((max_elems + 255) / 256, 1024), 1);
   const dim3 g((unsigned)gx, n_desc);
   if (elem_bytes == 8)
-    hipLaunchKernelGGL(k_bind<float2>, g, dim3(256), 0, s, (const float2*)leaves, (float2*)bound, descs, ctrl);
+    hipLaunchKernelGGL(k_bind<float2>, g, dim3(256), 0, s, (const float2*)leaves, (float2*)bound, descs, ctrl, n_desc,
+                       kappa);
   else
     hipLaunchKernelGGL(k_bind<uint32_t>, g, dim3(256), 0, s, (const uint32_t*)leaves, (uint32_t*)bound, descs,
-                       ctrl);
+                       ctrl, n_desc, kappa);
   return hipGetLastError();
 }
 
@@ -517,15 +534,24 @@ template <typename E>
 __global__ __launch_bounds__(256) void k_accum(const E* __restrict__ root, const Runs y2root, int n_open,
                                               double root_scale, Ctrl* ctrl, float* maxslots,
                                               const float* __restrict__ out_scales, int n_slots, float over,
-                                              float under) {
+                                              float under, double k0re, double k0im, int sliced_factors) {
   double* amp = ctrl->amp;
   const int64_t n = (int64_t)1 << n_open;
+  // factor of this slice: 2^e_root, the unsliced leaves' rounding factor and
+  // (left by the bind kernel) the sliced leaves' factor for this slice
+  double kr = k0re * root_scale, ki = k0im * root_scale;
+  if (sliced_factors) {
+    const double sr = ctrl->kap_re, si = ctrl->kap_im;
+    const double t = kr * sr - ki * si;
+    ki = kr * si + ki * sr;
+    kr = t;
+  }
   bool bad = false;
   for (int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; y < n; y += (int64_t)gridDim.x * blockDim.x) {
     const float2 v = to_f2(root[dep((uint64_t)y, y2root)]);
     bad |= !(isfinite(v.x) && isfinite(v.y));
-    amp[2 * y] += (double)v.x * root_scale;
-    amp[2 * y + 1] += (double)v.y * root_scale;
+    amp[2 * y] += (double)v.x * kr - (double)v.y * ki;
+    amp[2 * y + 1] += (double)v.x * ki + (double)v.y * kr;
   }
   if (bad) atomicOr(&ctrl->flags, (unsigned)TN_FLAG_NONFINITE);
   if (blockIdx.x == 0) {
@@ -542,20 +568,21 @@ __global__ __launch_bounds__(256) void k_accum(const E* __restrict__ root, const
 }
 
 hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,
-                        const float* out_scales, int n_slots, hipStream_t s) {
+                        const float* out_scales, int n_slots, bool sliced_factors, hipStream_t s) {
   const int64_t n = (int64_t)1 << d.n_open;
   const int64_t grid = std::min<int64_t>((n + 255) / 256, 4096);
   const dim3 g((unsigned)grid);
   const float under = 0.25f;
+  const int sf = sliced_factors ? 1 : 0;
   if (dtype == TN_DTYPE_F16S)
     hipLaunchKernelGGL(k_accum<cf16>, g, dim3(256), 0, s, (const cf16*)root, d.y2root, d.n_open, d.root_scale, ctrl,
-                       maxslots, out_scales, n_slots, 65504.f, under);
+                       maxslots, out_scales, n_slots, 65504.f, under, d.kappa0_re, d.kappa0_im, sf);
   else if (dtype == TN_DTYPE_BF16S)
     hipLaunchKernelGGL(k_accum<cbf16>, g, dim3(256), 0, s, (const cbf16*)root, d.y2root, d.n_open, d.root_scale,
-                       ctrl, maxslots, out_scales, n_slots, 3.0e38f, under);
+                       ctrl, maxslots, out_scales, n_slots, 3.0e38f, under, d.kappa0_re, d.kappa0_im, sf);
   else
     hipLaunchKernelGGL(k_accum<float2>, g, dim3(256), 0, s, (const float2*)root, d.y2root, d.n_open, d.root_scale,
-                       ctrl, maxslots, out_scales, 0, 3.0e38f, 0.f);
+                       ctrl, maxslots, out_scales, 0, 3.0e38f, 0.f, 1.0, 0.0, 0);
   return hipGetLastError();
 }
 

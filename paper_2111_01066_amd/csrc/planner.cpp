@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <set>
+#include <iomanip>
 #include <sstream>
 
 #include "internal.h"
@@ -297,7 +298,8 @@ void make_json(PlanCore& P) {
   json_ref(js, P.accum.root);
   js << ",\"y2root\":";
   json_runs(js, P.accum.y2root);
-  js << "}}";
+  js << std::setprecision(17) << ",\"root_scale\":" << P.accum.root_scale << ",\"rounding_factor\":["
+     << P.accum.kappa0_re << "," << P.accum.kappa0_im << "]}}";
   P.json = js.str();
 }
 

@@ -75,11 +75,18 @@ def test_batch_matches_per_plan_runs_and_oracle(small, dtype):
         err = oracle.relative_error_norm(got, small[i][5])
         assert err < TOL[dtype], (i, err)
         assert p.status() & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
-    # a second launch accumulates the same sums again (exact doubling)
+    # a second launch accumulates the same sums again, exactly as a second
+    # round of per-plan runs does
     b.run()
+    for p, a, n in zip(plans, seq, n_sl):
+        p.contract(0, n, a)
     torch.cuda.synchronize()
     for a, s in zip(amps, seq):
-        assert np.array_equal(a.cpu().numpy(), 2 * s.cpu().numpy())
+        got, ref = a.cpu().numpy(), s.cpu().numpy()
+        assert np.array_equal(got, ref)
+    for i, a in enumerate(amps):
+        err = oracle.relative_error_norm(a.cpu().numpy() / 2, small[i][5])
+        assert err < TOL[dtype], (i, err)
     b.close()
     for p in plans:
         p.close()

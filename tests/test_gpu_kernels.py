@@ -147,7 +147,10 @@ def test_permute_4byte_bit_exact(rank):
 @pytest.mark.parametrize("form", ["4m", "3m"])
 @pytest.mark.parametrize("M,N,K,batch,splits", [(128, 128, 16, 1, 1), (256, 384, 1024, 2, 1),
                                                 (128, 256, 4096, 1, 8), (512, 128, 96, 1, 1), (64, 192, 32, 1, 1),
-                                                (1280, 256, 128, 1, 1), (192, 320, 1024, 1, 4)])
+                                                (1280, 256, 128, 1, 1), (192, 320, 1024, 1, 4),
+                                                # 128x256 tiles (N a multiple of 256, K slabs >= 1024)
+                                                (256, 512, 2048, 1, 1), (128, 256, 8192, 1, 2),
+                                                (384, 768, 1024, 3, 1)])
 def test_cgemm_half(dtype, form, M, N, K, batch, splits):
     rng = np.random.default_rng(M + 3 * N + K)
     A = rng.standard_normal((batch, M, K)) + 1j * rng.standard_normal((batch, M, K))
