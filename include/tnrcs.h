@@ -167,6 +167,26 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps,
  * must be used by one stream at a time.  TN_E_UNSUPPORTED for dry-run plans. */
 int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream);
 
+/* Checked form of tn_contract_slices for scaled storage (the retry of the
+ * mixed-precision scheme): every slice is first contracted into plan-owned
+ * staging, the stream is synchronized and the slice's numeric flags are
+ * read.  A clean slice is then added to amp.  A slice that raised
+ * TN_FLAG_OVERFLOW or TN_FLAG_UNDERFLOW makes the plan recalibrate its output
+ * shifts on that slice (later slices keep the new shifts) and run it again
+ * once; if flags persist, or a NaN/Inf appears without a range flag (or in
+ * complex64), nothing of that slice is added, the flags stay set and the
+ * call returns TN_E_NUMERIC (slices before it are in amp).  *retries
+ * (may be NULL) receives the number of re-run slices.  Synchronous. */
+int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream,
+                               int32_t* retries);
+
+/* Scaled storage: adds delta (|delta| <= 64) to every step's calibrated output
+ * shift, i.e. scales every stored intermediate by 2^-delta (the results are
+ * unchanged up to rounding while the values stay in range).  A manual
+ * adjustment of the calibration, also used to test the range checks.
+ * TN_E_ARG for complex64 plans. */
+int tn_plan_shift_outputs(tn_plan_t p, int32_t delta);
+
 /* ---- batches of plans (many circuits in one launch) ---- */
 
 typedef struct tn_batch_s* tn_batch_t;

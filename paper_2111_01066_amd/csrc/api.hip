@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -86,6 +87,7 @@ struct tn_plan_s {
   float* d_maxslots = nullptr;
   float* d_outscales = nullptr;
   double2* d_kappa = nullptr;  // scaled storage: per sub-block rounding factors of the sliced leaves
+  double* d_stage = nullptr;   // checked runs: one slice's bunch before it joins the sum
   int64_t bind_max = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -283,14 +285,14 @@ static int enqueue_slice(tn_plan_s* p, hipStream_t s) {
 // recorded before any rounding), derive the shift that brings the largest
 // magnitude to 2^kTargetLog2, run it again so its stored output uses that
 // shift, and go on to the next op (whose inputs are now final).
-static int calibrate(tn_plan_s* p) {
+static int calibrate(tn_plan_s* p, int64_t slice = 0) {
   PlanCore& P = p->core;
   if (P.opts.dtype == TN_DTYPE_C64 || P.n_slots == 0) {
     propagate_exponents(P);
     return TN_OK;
   }
   hipStream_t s = nullptr;
-  HIP_TRY(launch_set_ctrl(p->d_ctrl, 0, nullptr, s), "control kernel");
+  HIP_TRY(launch_set_ctrl(p->d_ctrl, slice, nullptr, s), "control kernel");
   int rc = launch_bind_slice(p, s);
   if (rc) return rc;
   const float zero = 0.f;
@@ -359,6 +361,7 @@ static void release(tn_plan_s* p) {
   hipFree(p->d_maxslots);
   hipFree(p->d_outscales);
   if (p->d_kappa) hipFree(p->d_kappa);
+  if (p->d_stage) hipFree(p->d_stage);
 }
 
 extern "C" {
@@ -577,21 +580,9 @@ int tn_pair_run(tn_plan_t p, const void* A, const void* B, void* C, int64_t batc
   return TN_OK;
 }
 
-int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream) {
-  if (!p) return fail(TN_E_ARG, "plan is NULL");
-  if (p->core.pair_mode) return fail(TN_E_ARG, "pairwise plan: use tn_pair_run");
-  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
-  if (!amp) return fail(TN_E_ARG, "amp is NULL");
-  const int64_t ns = p->core.stats.n_slices;
-  if (s_begin < 0 || s_end < s_begin || s_end > ns)
-    return fail(TN_E_ARG, "slice range [" + std::to_string(s_begin) + ", " + std::to_string(s_end) +
-                              ") outside [0, " + std::to_string(ns) + ")");
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
-  p->last_stream = s;
-  p->ran = true;
-  if (s_end == s_begin) return TN_OK;
-  HIP_TRY(launch_set_ctrl(p->d_ctrl, s_begin, amp, s), "control kernel");
+// Runs `count` slices from the cursor on, replaying the per-slice graph
+// (captured on first use) or enqueueing the kernels directly.
+static int run_slices(tn_plan_s* p, int64_t count, hipStream_t s) {
   if (p->core.opts.use_graph) {
     if (!p->exec) {
       if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "create capture stream");
@@ -607,14 +598,111 @@ int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, v
       p->graph = g;
       HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate graph");
     }
-    for (int64_t sl = s_begin; sl < s_end; ++sl) HIP_TRY(hipGraphLaunch(p->exec, s), "graph launch");
+    for (int64_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(p->exec, s), "graph launch");
   } else {
-    for (int64_t sl = s_begin; sl < s_end; ++sl) {
+    for (int64_t i = 0; i < count; ++i) {
       int rc = enqueue_slice(p, s);
       if (rc) return rc;
     }
   }
   return TN_OK;
+}
+
+int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream) {
+  if (!p) return fail(TN_E_ARG, "plan is NULL");
+  if (p->core.pair_mode) return fail(TN_E_ARG, "pairwise plan: use tn_pair_run");
+  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
+  if (!amp) return fail(TN_E_ARG, "amp is NULL");
+  const int64_t ns = p->core.stats.n_slices;
+  if (s_begin < 0 || s_end < s_begin || s_end > ns)
+    return fail(TN_E_ARG, "slice range [" + std::to_string(s_begin) + ", " + std::to_string(s_end) +
+                              ") outside [0, " + std::to_string(ns) + ")");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  p->last_stream = s;
+  p->ran = true;
+  if (s_end == s_begin) return TN_OK;
+  HIP_TRY(launch_set_ctrl(p->d_ctrl, s_begin, amp, s), "control kernel");
+  return run_slices(p, s_end - s_begin, s);
+}
+
+int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream,
+                               int32_t* retries) {
+  if (!p) return fail(TN_E_ARG, "plan is NULL");
+  if (p->core.pair_mode) return fail(TN_E_ARG, "pairwise plan: use tn_pair_run");
+  if (p->core.opts.dry_run) return fail(TN_E_UNSUPPORTED, "dry-run plan has no device state");
+  if (!amp) return fail(TN_E_ARG, "amp is NULL");
+  const int64_t ns = p->core.stats.n_slices;
+  if (s_begin < 0 || s_end < s_begin || s_end > ns)
+    return fail(TN_E_ARG, "slice range [" + std::to_string(s_begin) + ", " + std::to_string(s_end) +
+                              ") outside [0, " + std::to_string(ns) + ")");
+  if (retries) *retries = 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  const int64_t n_amp = (int64_t)1 << p->core.accum.n_open;
+  if (!p->d_stage) HIP_TRY(hipMalloc((void**)&p->d_stage, (size_t)n_amp * 16), "alloc staging bunch");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+  if (p->ran && p->last_stream != s) HIP_TRY(hipStreamSynchronize(p->last_stream), "stream synchronize");
+  p->last_stream = s;
+  p->ran = true;
+  Ctrl c{};
+  HIP_TRY(hipMemcpy(&c, p->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost), "read control");
+  uint32_t sticky = c.flags;
+  const bool scaled = p->core.opts.dtype != TN_DTYPE_C64;
+  int rc = TN_OK;
+  for (int64_t sl = s_begin; sl < s_end && rc == TN_OK; ++sl) {
+    for (int attempt = 0;; ++attempt) {
+      HIP_TRY(hipMemsetAsync(p->d_stage, 0, (size_t)n_amp * 16, s), "clear staging bunch");
+      HIP_TRY(launch_set_ctrl(p->d_ctrl, sl, p->d_stage, s, true), "control kernel");
+      if ((rc = run_slices(p, 1, s))) break;
+      HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+      HIP_TRY(hipMemcpy(&c, p->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost), "read control");
+      const uint32_t range = c.flags & (TN_FLAG_OVERFLOW | TN_FLAG_UNDERFLOW);
+      if (c.flags == 0) {
+        HIP_TRY(launch_add_amp(p->d_stage, (double*)amp, n_amp, s), "add slice");
+        break;
+      }
+      if (scaled && range && attempt == 0) {
+        // the shifts calibrated on slice 0 do not fit this slice: calibrate
+        // on it (every later slice keeps the new shifts) and run it again
+        if ((rc = calibrate(p, sl))) break;
+        drop_graph(p);  // the captured kernels hold the old output scales
+        if (retries) ++*retries;
+        continue;
+      }
+      sticky |= c.flags;
+      rc = fail(TN_E_NUMERIC, "slice " + std::to_string(sl) + ": numeric flags " + std::to_string(c.flags) +
+                                  (attempt ? " persist after recalibration" : ""));
+      break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+  HIP_TRY(hipMemcpy(reinterpret_cast<char*>(p->d_ctrl) + offsetof(Ctrl, flags), &sticky, sizeof(uint32_t),
+                    hipMemcpyHostToDevice),
+          "restore flags");
+  return rc;
+}
+
+int tn_plan_shift_outputs(tn_plan_t p, int32_t delta) {
+  if (!p) return fail(TN_E_ARG, "plan is NULL");
+  PlanCore& P = p->core;
+  if (P.pair_mode) return fail(TN_E_ARG, "pairwise plan");
+  if (P.opts.dtype == TN_DTYPE_C64) return fail(TN_E_ARG, "complex64 plans have no output shifts");
+  if (delta < -64 || delta > 64) return fail(TN_E_ARG, "delta out of range");
+  for (Op& op : P.ops)
+    if (op.max_slot >= 0) {
+      op.s_out += delta;
+      const float sc = (float)std::ldexp(1.0, -op.s_out);
+      op.gemm.out_scale = sc;
+      op.idx.out_scale = sc;
+    }
+  propagate_exponents(P);
+  make_json(P);
+  if (P.opts.dry_run) return TN_OK;
+  HIP_TRY(hipSetDevice(p->device), "hipSetDevice");
+  if (p->ran) HIP_TRY(hipStreamSynchronize(p->last_stream), "stream synchronize");
+  drop_graph(p);
+  return upload_scales(p);
 }
 
 int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, void* const* amps, tn_batch_t* out) {

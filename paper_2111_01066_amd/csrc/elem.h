@@ -47,6 +47,13 @@ __device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
   return o;
 }
 
+// Running maximum of |re|, |im| for the range check of scaled storage; a
+// NaN counts as +inf (it comes from an overflow earlier in the same sum).
+__device__ __forceinline__ float mag_max(float m, float re, float im) {
+  if (re != re || im != im) return INFINITY;
+  return fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+}
+
 // Largest |component| over a workgroup, folded into *slot (non-negative
 // floats order like their bit patterns).  One atomic per workgroup at most,
 // and none once the record already holds a larger value.  Every thread of

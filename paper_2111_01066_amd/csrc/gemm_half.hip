@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm(const E* __restrict__ A, con
         if (to_work) {
           reinterpret_cast<float2*>(Cout)[z * sC + o] = make_float2(re, im);
         } else {
-          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+          mx = mag_max(mx, re, im);
           reinterpret_cast<E*>(Cout)[z * sC + o] = from_f2<E>(re * out_scale, im * out_scale);
         }
       }
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_hsplit_sum(const float2* __restrict__ W
       r += v.x;
       im += v.y;
     }
-    mx = fmaxf(mx, fmaxf(fabsf(r), fabsf(im)));
+    mx = mag_max(mx, r, im);
     C[i] = from_f2<E>(r * out_scale, im * out_scale);
   }
   record_max(maxslot, mx);

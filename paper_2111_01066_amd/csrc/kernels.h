@@ -18,7 +18,9 @@ struct Ctrl {
 
 inline int elem_bytes_of(int dtype) { return dtype == TN_DTYPE_C64 ? 8 : 4; }
 
-hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s);
+hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s, bool clear_flags = false);
+// dst += src over n complex128 entries.
+hipError_t launch_add_amp(const double* src, double* dst, int64_t n, hipStream_t s);
 // Copies every sliced leaf's sub-block of the current slice; with kappa
 // (scaled storage) also stores the product of their rounding factors in ctrl.
 hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,

@@ -22,13 +22,28 @@ namespace tnrcs {
 
 // ---------------------------------------------------------------- control --
 
-__global__ void k_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp) {
+__global__ void k_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, int clear_flags) {
   ctrl->cursor = cursor;
   ctrl->amp = (double*)amp;
+  if (clear_flags) ctrl->flags = 0u;
 }
 
-hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(1), 0, s, ctrl, cursor, amp);
+hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s, bool clear_flags) {
+  hipLaunchKernelGGL(k_set_ctrl, dim3(1), dim3(1), 0, s, ctrl, cursor, amp, clear_flags ? 1 : 0);
+  return hipGetLastError();
+}
+
+// dst[i] += src[i] over n complex128 entries (a checked slice joins the sum).
+__global__ __launch_bounds__(256) void k_add_amp(const double* __restrict__ src, double* __restrict__ dst,
+                                                int64_t n2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+
+hipError_t launch_add_amp(const double* src, double* dst, int64_t n, hipStream_t s) {
+  const int64_t n2 = 2 * n;
+  hipLaunchKernelGGL(k_add_amp, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n2 + 255) / 256, 4096))),
+                     dim3(256), 0, s, src, dst, n2);
   return hipGetLastError();
 }
 
@@ -291,7 +306,7 @@ __global__ __launch_bounds__(256) void k_generic(const E* __restrict__ A, const 
       im = fmaf(x.x, y.y, im);
       im = fmaf(x.y, y.x, im);
     }
-    mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+    mx = mag_max(mx, re, im);
     C[c] = from_f2<E>(re * op.out_scale, im * op.out_scale);
   }
   record_max(maxslot, mx);
@@ -357,7 +372,7 @@ __global__ __launch_bounds__(256) void k_skinny(const E* __restrict__ A, const E
     E* c = C + m * NN;
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      mx = fmaxf(mx, fmaxf(fabsf(re[n]), fabsf(im[n])));
+      mx = mag_max(mx, re[n], im[n]);
       c[n] = from_f2<E>(re[n] * op.out_scale, im[n] * op.out_scale);
     }
   }
@@ -486,7 +501,7 @@ __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__
       __syncthreads();
     }
     if (tid == 0) {
-      mx = fmaxf(mx, fmaxf(fabsf(red[0][0]), fabsf(red[1][0])));
+      mx = mag_max(mx, red[0][0], red[1][0]);
       C[o] = from_f2<E>(red[0][0] * out_scale, red[1][0] * out_scale);
     }
     __syncthreads();

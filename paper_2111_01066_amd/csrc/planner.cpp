@@ -277,8 +277,8 @@ void make_json(PlanCore& P) {
       js << "]";
     } else if (op.kind == kOpGemm) {
       js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
-         << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"split_max\":" << op.gemm.split_max << ",\"occ\":" << op.gemm.occ << ",\"s_out\":" << op.s_out
-         << ",\"w\":";
+         << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"split_max\":"
+         << op.gemm.split_max << ",\"occ\":" << op.gemm.occ << ",\"s_out\":" << op.s_out << ",\"w\":";
       json_ref(js, op.w);
     } else {
       js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";

@@ -91,6 +91,8 @@ _lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c
                                ctypes.c_float, c_void_p, c_int32, c_void_p, c_void_p]
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                               c_void_p, c_int32, c_void_p]
+_lib.tn_contract_slices_checked.argtypes = [c_void_p, c_int64, c_int64, c_void_p, c_void_p, POINTER(c_int32)]
+_lib.tn_plan_shift_outputs.argtypes = [c_void_p, c_int32]
 _lib.tn_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_void_p), POINTER(c_void_p)]
 _lib.tn_batch_run.argtypes = [c_void_p, c_void_p]
 _lib.tn_batch_destroy.argtypes = [c_void_p]
@@ -101,7 +103,7 @@ _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_v
 
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
-            "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
+            "tn_contract_slices_checked", "tn_plan_shift_outputs", "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
             "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
 
 
@@ -201,6 +203,17 @@ class Plan:
         """tn_contract_slices: amp (device complex128, 2^n_open) += sum of slices."""
         _check(_lib.tn_contract_slices(self._h, int(s_begin), int(s_end), c_void_p(_ptr(amp)),
                                        c_void_p(_stream(stream))))
+
+    def contract_checked(self, s_begin: int, s_end: int, amp, stream=None) -> int:
+        """tn_contract_slices_checked; returns the number of re-run slices."""
+        r = c_int32()
+        _check(_lib.tn_contract_slices_checked(self._h, int(s_begin), int(s_end), c_void_p(_ptr(amp)),
+                                               c_void_p(_stream(stream)), byref(r)))
+        return int(r.value)
+
+    def shift_outputs(self, delta: int):
+        """tn_plan_shift_outputs (scaled storage)."""
+        _check(_lib.tn_plan_shift_outputs(self._h, int(delta)))
 
     def info(self) -> dict:
         s = tn_plan_stats()

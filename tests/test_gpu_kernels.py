@@ -150,7 +150,9 @@ def test_permute_4byte_bit_exact(rank):
                                                 (1280, 256, 128, 1, 1), (192, 320, 1024, 1, 4),
                                                 # 128x256 tiles (N a multiple of 256, K slabs >= 1024)
                                                 (256, 512, 2048, 1, 1), (128, 256, 8192, 1, 2),
-                                                (384, 768, 1024, 3, 1)])
+                                                (384, 768, 1024, 3, 1),
+                                                # long K: one wave per SIMD, 64-deep stages
+                                                (128, 128, 16384, 1, 1), (256, 128, 65536, 1, 2)])
 def test_cgemm_half(dtype, form, M, N, K, batch, splits):
     rng = np.random.default_rng(M + 3 * N + K)
     A = rng.standard_normal((batch, M, K)) + 1j * rng.standard_normal((batch, M, K))

@@ -165,3 +165,17 @@ def test_tuning_reserves_split_workspace_in_the_plan():
         if b["split_max"] > 1:
             assert b["K"] // b["split_max"] >= 256 and b["split_max"] * b["M"] * b["N"] <= 2 ** 28
     assert tuned.info()["arena_bytes"] >= base.info()["arena_bytes"]
+
+
+def test_shift_outputs_on_dry_run_plan():
+    c = make_rqc(3, 4, 8, seed=1)
+    open_q = [0, 5, 11]
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    plan = tnrcs.Plan(c, pairs, [], open_q, None, dtype="f16s", dry_run=True)
+    before = [o["s_out"] for o in plan.json()["ops"] if o["kind"] != 0]
+    plan.shift_outputs(3)
+    after = [o["s_out"] for o in plan.json()["ops"] if o["kind"] != 0]
+    assert before and after == [s + 3 for s in before]
+    with pytest.raises(tnrcs.TnError):
+        plan.shift_outputs(100)
