@@ -180,12 +180,16 @@ int tn_contract_slices(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, v
 int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void* amp, void* stream,
                                int32_t* retries);
 
-/* Scaled storage: adds delta (|delta| <= 64) to every step's calibrated output
- * shift, i.e. scales every stored intermediate by 2^-delta (the results are
- * unchanged up to rounding while the values stay in range).  A manual
- * adjustment of the calibration, also used to test the range checks.
- * TN_E_ARG for complex64 plans. */
-int tn_plan_shift_outputs(tn_plan_t p, int32_t delta);
+/* Scaled storage: adds delta (|delta| <= 64) to the calibrated output shift
+ * of kernel `op` (its index in the plan's kernel list, see tn_plan_json), or
+ * of every producing kernel if op < 0.  The kernel's stored result is scaled
+ * by 2^-delta relative to its stored inputs, so the change carries along the
+ * contraction tree (with op < 0 it compounds with depth); the exponents are
+ * updated so the results are unchanged, exactly so while every value stays in
+ * the format's normal range.  A manual adjustment of the calibration, also
+ * used to test the range checks.  TN_E_ARG for complex64 plans, for a kernel
+ * without an output shift (a permute) or an index out of range. */
+int tn_plan_shift_outputs(tn_plan_t p, int32_t op, int32_t delta);
 
 /* ---- batches of plans (many circuits in one launch) ---- */
 
@@ -295,7 +299,7 @@ int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, in
  * cores with FP32 accumulation, for scaled storage: A, B, C hold (re, im)
  * pairs of the 16-bit format; C = round(out_scale * A B^T) with the same
  * shapes, layouts and batch convention as tn_cgemm_c64; M, N multiples of
- * 128, K a multiple of 16.  If max_out (device float, non-NULL) is given, the
+ * 64, K a multiple of 16.  If max_out (device float, non-NULL) is given, the
  * largest |component| of A B^T (before scaling) is folded into it with an
  * atomic maximum (it must start at 0 or a smaller value).  splits > 1 as in
  * tn_cgemm_c64 (work: splits*M*N complex64 entries). */

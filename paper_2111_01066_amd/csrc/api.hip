@@ -683,19 +683,22 @@ int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void
   return rc;
 }
 
-int tn_plan_shift_outputs(tn_plan_t p, int32_t delta) {
+int tn_plan_shift_outputs(tn_plan_t p, int32_t op_index, int32_t delta) {
   if (!p) return fail(TN_E_ARG, "plan is NULL");
   PlanCore& P = p->core;
   if (P.pair_mode) return fail(TN_E_ARG, "pairwise plan");
   if (P.opts.dtype == TN_DTYPE_C64) return fail(TN_E_ARG, "complex64 plans have no output shifts");
   if (delta < -64 || delta > 64) return fail(TN_E_ARG, "delta out of range");
-  for (Op& op : P.ops)
-    if (op.max_slot >= 0) {
-      op.s_out += delta;
-      const float sc = (float)std::ldexp(1.0, -op.s_out);
-      op.gemm.out_scale = sc;
-      op.idx.out_scale = sc;
-    }
+  if (op_index >= (int32_t)P.ops.size()) return fail(TN_E_ARG, "kernel index out of range");
+  if (op_index >= 0 && P.ops[op_index].max_slot < 0) return fail(TN_E_ARG, "kernel has no output shift");
+  for (size_t i = 0; i < P.ops.size(); ++i) {
+    Op& op = P.ops[i];
+    if (op.max_slot < 0 || (op_index >= 0 && (int32_t)i != op_index)) continue;
+    op.s_out += delta;
+    const float sc = (float)std::ldexp(1.0, -op.s_out);
+    op.gemm.out_scale = sc;
+    op.idx.out_scale = sc;
+  }
   propagate_exponents(P);
   make_json(P);
   if (P.opts.dry_run) return TN_OK;

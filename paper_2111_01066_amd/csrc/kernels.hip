@@ -286,25 +286,41 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
 // ---------------------------------------------------------------- generic --
 // One output element per thread: C[(m<<nN)|n] = sum_k A[dep(m)|dep(k)] B[dep(n)|dep(k)],
 // accumulated in FP32, multiplied by the op's output scale before storage.
+// The K offsets of both operands are tabulated once per block in LDS for the
+// low kTabBits bits of k (dep is additive over disjoint bit ranges), so the
+// inner loop is two LDS reads and two gathered loads per term.
+
+constexpr int kTabBits = 10;
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_generic(const E* __restrict__ A, const E* __restrict__ B,
                                                 E* __restrict__ C, const IndexOp op, float* maxslot) {
+  __shared__ uint64_t atab[1 << kTabBits], btab[1 << kTabBits];
+  const int lo_bits = op.nK < kTabBits ? op.nK : kTabBits;
+  const int n_lo = 1 << lo_bits;
+  for (int k = threadIdx.x; k < n_lo; k += blockDim.x) {
+    atab[k] = dep((uint64_t)k, op.aK);
+    btab[k] = dep((uint64_t)k, op.bK);
+  }
+  __syncthreads();
   const int64_t nC = (int64_t)1 << (op.nM + op.nN);
-  const int64_t nK = (int64_t)1 << op.nK;
+  const int64_t n_hi = (int64_t)1 << (op.nK - lo_bits);
   const uint64_t nmask = (1ull << op.nN) - 1ull;
   float mx = 0.f;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nC; c += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t m = (uint64_t)c >> op.nN, n = (uint64_t)c & nmask;
     const uint64_t ab = dep(m, op.aM), bb = dep(n, op.bN);
     float re = 0.f, im = 0.f;
-    for (int64_t k = 0; k < nK; ++k) {
-      const float2 x = to_f2(A[ab | dep((uint64_t)k, op.aK)]);
-      const float2 y = to_f2(B[bb | dep((uint64_t)k, op.bK)]);
-      re = fmaf(x.x, y.x, re);
-      re = fmaf(-x.y, y.y, re);
-      im = fmaf(x.x, y.y, im);
-      im = fmaf(x.y, y.x, im);
+    for (int64_t h = 0; h < n_hi; ++h) {
+      const uint64_t ah = ab | dep((uint64_t)h << lo_bits, op.aK), bh = bb | dep((uint64_t)h << lo_bits, op.bK);
+      for (int k = 0; k < n_lo; ++k) {
+        const float2 x = to_f2(A[ah | atab[k]]);
+        const float2 y = to_f2(B[bh | btab[k]]);
+        re = fmaf(x.x, y.x, re);
+        re = fmaf(-x.y, y.y, re);
+        im = fmaf(x.x, y.y, im);
+        im = fmaf(x.y, y.x, im);
+      }
     }
     mx = mag_max(mx, re, im);
     C[c] = from_f2<E>(re * op.out_scale, im * op.out_scale);
@@ -427,52 +443,79 @@ hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const
 // K bits are the operands' low bits), the block reduces in LDS, and one
 // block sums the FP32 per-block partials in a fixed order.
 
-template <int NOUT, typename E>
+template <int NN, typename E>
 __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, const E* __restrict__ B,
                                                     float2* __restrict__ part, const IndexOp op) {
-  __shared__ uint64_t am[NOUT], bn[NOUT];
+  // outputs (m, n): m < nm = 2^nM <= 64 / NN, n < NN = 2^nN; each k loads
+  // every A entry (one per m) and every B entry (one per n) once
+  constexpr int NM = 64 / NN;
+  __shared__ uint64_t am[NM], bn[NN];
   __shared__ float red[2][256];
-  const int nout = 1 << (op.nM + op.nN);
-  const uint64_t nmask = (1ull << op.nN) - 1ull;
+  const int nm = 1 << op.nM;
   const int tid = threadIdx.x;
-  if (tid < nout) {
-    am[tid] = dep((uint64_t)tid >> op.nN, op.aM);
-    bn[tid] = dep((uint64_t)tid & nmask, op.bN);
-  }
+  if (tid < nm) am[tid] = dep((uint64_t)tid, op.aM);
+  if (tid < NN) bn[tid] = dep((uint64_t)tid, op.bN);
   __syncthreads();
-  float acc_r[NOUT], acc_i[NOUT];
+  float acc_r[NM][NN], acc_i[NM][NN];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) acc_r[o] = acc_i[o] = 0.f;
+  for (int i = 0; i < NM; ++i)
+#pragma unroll
+    for (int j = 0; j < NN; ++j) acc_r[i][j] = acc_i[i][j] = 0.f;
   const int64_t nK = (int64_t)1 << op.nK;
   for (int64_t k = (int64_t)blockIdx.x * 256 + tid; k < nK; k += (int64_t)gridDim.x * 256) {
     const uint64_t ak = dep((uint64_t)k, op.aK), bk = dep((uint64_t)k, op.bK);
+    if constexpr (NN <= 8) {  // keep the B entries, stream the A entries
+      float2 y[NN];
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-      if (o < nout) {
-        const float2 x = to_f2(A[am[o] | ak]);
-        const float2 y = to_f2(B[bn[o] | bk]);
-        acc_r[o] = fmaf(x.x, y.x, acc_r[o]);
-        acc_r[o] = fmaf(-x.y, y.y, acc_r[o]);
-        acc_i[o] = fmaf(x.x, y.y, acc_i[o]);
-        acc_i[o] = fmaf(x.y, y.x, acc_i[o]);
+      for (int j = 0; j < NN; ++j) y[j] = to_f2(B[bn[j] | bk]);
+#pragma unroll
+      for (int i = 0; i < NM; ++i) {
+        if (i < nm) {  // uniform across the grid
+          const float2 x = to_f2(A[am[i] | ak]);
+#pragma unroll
+          for (int j = 0; j < NN; ++j) {
+            acc_r[i][j] = fmaf(x.x, y[j].x, acc_r[i][j]);
+            acc_r[i][j] = fmaf(-x.y, y[j].y, acc_r[i][j]);
+            acc_i[i][j] = fmaf(x.x, y[j].y, acc_i[i][j]);
+            acc_i[i][j] = fmaf(x.y, y[j].x, acc_i[i][j]);
+          }
+        }
+      }
+    } else {  // few m (NM <= 4): keep the A entries, stream the B entries
+      float2 x[NM];
+#pragma unroll
+      for (int i = 0; i < NM; ++i) x[i] = i < nm ? to_f2(A[am[i] | ak]) : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < NN; ++j) {
+        const float2 y = to_f2(B[bn[j] | bk]);
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+          acc_r[i][j] = fmaf(x[i].x, y.x, acc_r[i][j]);
+          acc_r[i][j] = fmaf(-x[i].y, y.y, acc_r[i][j]);
+          acc_i[i][j] = fmaf(x[i].x, y.y, acc_i[i][j]);
+          acc_i[i][j] = fmaf(x[i].y, y.x, acc_i[i][j]);
+        }
       }
     }
   }
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) {
-    if (o < nout) {  // uniform across the block
-      red[0][tid] = acc_r[o];
-      red[1][tid] = acc_i[o];
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) {
-          red[0][tid] += red[0][tid + w];
-          red[1][tid] += red[1][tid + w];
+  for (int i = 0; i < NM; ++i) {
+    if (i < nm) {
+#pragma unroll
+      for (int j = 0; j < NN; ++j) {
+        red[0][tid] = acc_r[i][j];
+        red[1][tid] = acc_i[i][j];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+          if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+          }
+          __syncthreads();
         }
+        if (tid == 0) part[(int64_t)blockIdx.x * (nm * NN) + i * NN + j] = make_float2(red[0][0], red[1][0]);
         __syncthreads();
       }
-      if (tid == 0) part[(int64_t)blockIdx.x * nout + o] = make_float2(red[0][0], red[1][0]);
-      __syncthreads();
     }
   }
 }
@@ -516,12 +559,16 @@ static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const In
                             hipStream_t s) {
   const int nout = 1 << (op.nM + op.nN);
   const int64_t g = splitk_blocks(op);
-  if (nout <= 4)
-    hipLaunchKernelGGL((k_splitk_part<4, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
-  else if (nout <= 16)
-    hipLaunchKernelGGL((k_splitk_part<16, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
-  else
-    hipLaunchKernelGGL((k_splitk_part<64, E>), dim3((unsigned)g), dim3(256), 0, s, A, B, part, op);
+  const dim3 grid((unsigned)g), blk(256);
+  switch (op.nN) {
+    case 0: hipLaunchKernelGGL((k_splitk_part<1, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 1: hipLaunchKernelGGL((k_splitk_part<2, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 2: hipLaunchKernelGGL((k_splitk_part<4, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 3: hipLaunchKernelGGL((k_splitk_part<8, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 4: hipLaunchKernelGGL((k_splitk_part<16, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 5: hipLaunchKernelGGL((k_splitk_part<32, E>), grid, blk, 0, s, A, B, part, op); break;
+    default: hipLaunchKernelGGL((k_splitk_part<64, E>), grid, blk, 0, s, A, B, part, op); break;
+  }
   hipLaunchKernelGGL(k_splitk_final<E>, dim3(1), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot);
 }
 

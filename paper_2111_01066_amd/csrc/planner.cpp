@@ -578,7 +578,8 @@ int build_plan(PlanCore& P, std::string& err) {
     const bool half = P.opts.dtype != TN_DTYPE_C64;
     const double eb = elem_bytes_plan(P);
     const int64_t f2 = 8 / (int64_t)eb;  // plan elements per float2 workspace entry
-    const bool dense = half ? (nM >= 7 && nN >= 7 && nK >= 4) : (nM >= 6 && nN >= 6 && nK >= 4);
+    // dense: both free extents at least 64 (the smallest GEMM tile) and K at least 16
+    const bool dense = nM >= 6 && nN >= 6 && nK >= 4;
     if (dense) {
       // K order: keep whichever operand already has K as its lowest block
       auto k_low_block = [&](const std::vector<int>& Lx2, std::vector<int>& kord) {

@@ -92,7 +92,7 @@ _lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                               c_void_p, c_int32, c_void_p]
 _lib.tn_contract_slices_checked.argtypes = [c_void_p, c_int64, c_int64, c_void_p, c_void_p, POINTER(c_int32)]
-_lib.tn_plan_shift_outputs.argtypes = [c_void_p, c_int32]
+_lib.tn_plan_shift_outputs.argtypes = [c_void_p, c_int32, c_int32]
 _lib.tn_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_void_p), POINTER(c_void_p)]
 _lib.tn_batch_run.argtypes = [c_void_p, c_void_p]
 _lib.tn_batch_destroy.argtypes = [c_void_p]
@@ -211,9 +211,9 @@ class Plan:
                                                c_void_p(_stream(stream)), byref(r)))
         return int(r.value)
 
-    def shift_outputs(self, delta: int):
-        """tn_plan_shift_outputs (scaled storage)."""
-        _check(_lib.tn_plan_shift_outputs(self._h, int(delta)))
+    def shift_outputs(self, delta: int, op: int = -1):
+        """tn_plan_shift_outputs (scaled storage): kernel `op`, or all if op < 0."""
+        _check(_lib.tn_plan_shift_outputs(self._h, int(op), int(delta)))
 
     def info(self) -> dict:
         s = tn_plan_stats()

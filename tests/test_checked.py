@@ -86,3 +86,36 @@ def test_shift_outputs_rejects_complex64(net):
         p.shift_outputs(1)
     assert e.value.code == -1
     p.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+def test_power_of_two_shift_is_exact(net, dtype):
+    """Scaled storage is exact under a power-of-two change of one exponent:
+    moving one kernel's output shift by +-1 doubles or halves every stored
+    value downstream of it and the root exponent compensates, so while
+    nothing leaves the normal range the amplitudes are bitwise identical.
+    Checked for the kernels whose stored results stay far from the range
+    limits (all but those that produce the root)."""
+    n = None
+    ref = None
+    p = _plan(net, dtype)
+    n = p.info()["n_slices"]
+    ops = p.json()["ops"]
+    a = _zeros()
+    p.contract(0, n, a)
+    torch.cuda.synchronize()
+    ref = a.cpu().numpy()
+    p.close()
+    producing = [i for i, o in enumerate(ops) if o["kind"] != 0]
+    assert len(producing) >= 4
+    for i in producing[:4]:
+        for delta in (1, -1):
+            print(f"shift +-1 exactness {dtype}: kernel {i} delta {delta}", flush=True)
+            p = _plan(net, dtype)
+            p.shift_outputs(delta, op=i)
+            a = _zeros()
+            p.contract(0, n, a)
+            torch.cuda.synchronize()
+            assert p.status() == 0
+            assert np.array_equal(a.cpu().numpy(), ref), (i, delta)
+            p.close()

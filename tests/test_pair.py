@@ -18,6 +18,16 @@ CASES = [
      [12, 13]),
     ([5, 1, 7, 3], [3, 8, 5, 9], [9, 7, 8, 1]),
     ([0, 1, 2], [3, 4], [3, 0, 4, 1, 2]),
+    # split-K: 64 outputs all on B's side, all on A's side, and 3+3 with interleaved K bits
+    (list(range(12)), [20, 21, 22, 23, 24, 25] + list(range(12)), [20, 21, 22, 23, 24, 25]),
+    ([30, 31, 32, 33, 34, 35] + list(range(11)), list(range(11)), [30, 31, 32, 33, 34, 35]),
+    ([0, 40, 1, 2, 41, 3, 4, 5, 42, 6, 7, 8, 9, 10, 11], [43, 0, 1, 44, 2, 3, 4, 5, 6, 45, 7, 8, 9, 10, 11],
+     [40, 41, 42, 43, 44, 45]),
+    # gathered: long K with few outputs per side (K tabulated in two levels), and K = 8 with many outputs
+    ([50, 51, 52] + list(range(13)), [53, 54, 55, 56, 57] + list(range(13)), [50, 53, 51, 54, 52, 55, 56, 57]),
+    (list(range(60, 70)) + [0, 1, 2], list(range(70, 79)) + [0, 1, 2], list(range(60, 70)) + list(range(70, 79))),
+    # dense with 64-wide free extents (the 64x64 GEMM tile, FP16 included)
+    (list(range(80, 88)) + list(range(6)), list(range(90, 96)) + list(range(6)), list(range(80, 88)) + list(range(90, 96))),
 ]
 
 

@@ -177,5 +177,15 @@ def test_shift_outputs_on_dry_run_plan():
     plan.shift_outputs(3)
     after = [o["s_out"] for o in plan.json()["ops"] if o["kind"] != 0]
     assert before and after == [s + 3 for s in before]
+    ops = plan.json()["ops"]
+    i = next(j for j, o in enumerate(ops) if o["kind"] != 0)
+    plan.shift_outputs(-2, op=i)
+    assert plan.json()["ops"][i]["s_out"] == ops[i]["s_out"] - 2
     with pytest.raises(tnrcs.TnError):
         plan.shift_outputs(100)
+    with pytest.raises(tnrcs.TnError):
+        plan.shift_outputs(1, op=len(ops))
+    perm = [j for j, o in enumerate(ops) if o["kind"] == 0]
+    if perm:
+        with pytest.raises(tnrcs.TnError):
+            plan.shift_outputs(1, op=perm[0])
