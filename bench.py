@@ -151,6 +151,17 @@ def kernel_split(res, dtype):
     return by_kind, split
 
 
+def slice_roofline_frac(res, dtype):
+    """Sum over the slice's kernels of max(flops / MFMA peak, bytes / HBM peak)
+    divided by the measured time per slice (GEMM flops as issued: 6MNK in the
+    3M form, 8MNK in 4M)."""
+    t = 0.0
+    for o in res["ops"]:
+        fl = o["flops"] * (0.75 if o["kind"] == 1 and o.get("form") == 2 else 1.0)
+        t += max(fl / (PEAK[dtype] * 1e12), o["bytes"] / (PEAK_HBM * 1e9))
+    return t / res["sec_per_slice"]
+
+
 def roofline(by_kind, dtype):
     dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
     d = by_kind[dom]
@@ -185,6 +196,38 @@ def micro(tnrcs, torch, np):
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
+
+    # machine ceilings: MFMA issue loops and a streaming copy of our own
+    probe_out = torch.empty(tnrcs.tn_probe_mfma_out_floats(), dtype=torch.float32, device="cuda")
+    for kind, iters, peak in (("f32", 100000, PEAK["c64"]), ("f16", 200000, PEAK["f16s"]),
+                              ("bf16", 200000, PEAK["bf16s"])):
+        tnrcs.tn_probe_mfma(kind, 1000, probe_out)
+        fl = [0.0]
+        ms = timed(lambda: fl.__setitem__(0, tnrcs.tn_probe_mfma(kind, iters, probe_out)), n=3)
+        tf = fl[0] / ms / 1e9
+        out[f"mfma_loop_{kind}"] = {"TFLOP/s": tf, "frac_peak": tf / peak}
+        log(f"[bench] MFMA issue loop {kind}: {tf:.1f} TFLOP/s ({tf / peak:.1%} of the {peak:.1f} TFLOP/s peak)")
+    del probe_out
+    nb = 4 << 30
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: tnrcs.tn_probe_copy(src, dst, nb))
+    assert torch.equal(src[:1024], dst[:1024])
+    gbs = 2.0 * nb / ms / 1e6
+    out["stream_copy_4GiB"] = {"GB/s": gbs, "frac_hbm": gbs / PEAK_HBM}
+    log(f"[bench] streaming copy (16-byte accesses): {gbs:.0f} GB/s ({gbs / PEAK_HBM:.1%} of 8 TB/s)")
+    del src, dst
+    # FP16 subnormal inputs in MFMA: A = 2^-20 (subnormal), B = 1, K = 16
+    dA = torch.zeros(128, 16, 2, dtype=torch.float16, device="cuda")
+    dA[..., 0] = 2.0 ** -20
+    dB = torch.zeros(128, 16, 2, dtype=torch.float16, device="cuda")
+    dB[..., 0] = 1.0
+    dC = torch.empty(128, 128, 2, dtype=torch.float16, device="cuda")
+    tnrcs.tn_cgemm_half("f16s", dA, dB, dC, 128, 128, 16, 1, "4m", out_scale=2.0 ** 20)
+    torch.cuda.synchronize()
+    v = float(dC[0, 0, 0].float().item())
+    out["fp16_mfma_subnormal_inputs"] = "kept" if abs(v - 16.0) < 1e-3 else f"not kept (got {v})"
+    log(f"[bench] FP16 MFMA with subnormal inputs: {out['fp16_mfma_subnormal_inputs']}")
 
     rng = np.random.default_rng(0)
     r = 30
@@ -491,6 +534,7 @@ def main():
             "graph": not args.no_graph,
             "kernels_per_slice": info["n_kernels"],
             "kernel_split": split,
+            "slice_roofline_frac": slice_roofline_frac(main_res, args.dtype),
             "numeric_flags": main_res["flags"],
         },
         "roofline": roof,

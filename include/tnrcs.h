@@ -307,6 +307,22 @@ int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t 
                   int64_t batch, int32_t form, float out_scale, void* work, int32_t splits, void* max_out,
                   void* stream);
 
+/* ---- measurement probes (the machine ceilings the kernels are compared with) ---- */
+
+/* MFMA issue loop with no memory traffic: kind 0 = v_mfma_f32_32x32x2_f32,
+ * 1 = v_mfma_f32_32x32x16_f16, 2 = v_mfma_f32_32x32x16_bf16; every wave of a
+ * fixed grid issues `iters` (1..2^24) rounds of 4 independent MFMAs.  *flops
+ * (host) receives the flops issued; out_dev (device float[
+ * tn_probe_mfma_out_floats()]) receives per-thread sums.  Asynchronous on
+ * `stream`; time it with events. */
+int tn_probe_mfma(int32_t kind, int64_t iters, void* out_dev, double* flops, void* stream);
+int64_t tn_probe_mfma_out_floats(void);
+
+/* Streaming device copy (16-byte loads and nontemporal stores) of `bytes`
+ * (a multiple of 16; both pointers 16-byte aligned, not overlapping), the
+ * HBM ceiling of the data-movement kernels.  Asynchronous on `stream`. */
+int tn_probe_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
 /* FP64 reductions over an amplitude buffer (complex128, device):
  *  out[0] = sum |a|^2 over n entries (the norm of an all-open run). */
 int tn_amp_norm2(const void* amp, int64_t n, void* out_dev, void* stream);

@@ -959,6 +959,25 @@ int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, in
   return TN_OK;
 }
 
+int64_t tn_probe_mfma_out_floats(void) { return mfma_peak_out_floats(); }
+
+int tn_probe_mfma(int32_t kind, int64_t iters, void* out_dev, double* flops, void* stream) {
+  if (kind < 0 || kind > 2) return fail(TN_E_ARG, "kind must be 0, 1 or 2");
+  if (iters < 1 || iters > ((int64_t)1 << 24)) return fail(TN_E_ARG, "iters out of range");
+  if (!out_dev || !flops) return fail(TN_E_ARG, "NULL argument");
+  HIP_TRY(launch_mfma_peak(kind, iters, (float*)out_dev, flops, (hipStream_t)stream), "MFMA probe");
+  return TN_OK;
+}
+
+int tn_probe_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  if (!src || !dst) return fail(TN_E_ARG, "NULL argument");
+  if (bytes < 0 || bytes % 16) return fail(TN_E_ARG, "bytes must be a non-negative multiple of 16");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return fail(TN_E_ARG, "buffers must be 16-byte aligned");
+  HIP_TRY(launch_stream_copy(src, dst, bytes / 16, (hipStream_t)stream), "copy probe");
+  return TN_OK;
+}
+
 int tn_amp_norm2(const void* amp, int64_t n, void* out_dev, void* stream) {
   if (!amp || !out_dev || n < 0) return fail(TN_E_ARG, "bad argument");
   hipError_t e = launch_norm2((const double*)amp, n, (double*)out_dev, (hipStream_t)stream);

@@ -55,6 +55,12 @@ hipError_t launch_xeb(const double* amp, int64_t n, const int64_t* idx, int64_t 
 hipError_t launch_hist(const double* amp, int64_t n, double scale, double xmax, int n_bins,
                        unsigned long long* counts, hipStream_t s);
 
+// probes: MFMA issue loop (kind 0 FP32, 1 FP16, 2 BF16; *flops = flops issued),
+// streaming copy of n16 16-byte units
+hipError_t launch_mfma_peak(int kind, int64_t iters, float* out, double* flops, hipStream_t s);
+int64_t mfma_peak_out_floats();
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, hipStream_t s);
+
 bool gemm_shape_ok(int64_t M, int64_t N, int64_t K);
 bool hgemm_shape_ok(int64_t M, int64_t N, int64_t K);
 

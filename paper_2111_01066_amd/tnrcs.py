@@ -97,6 +97,9 @@ _lib.tn_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), P
 _lib.tn_batch_run.argtypes = [c_void_p, c_void_p]
 _lib.tn_batch_destroy.argtypes = [c_void_p]
 _lib.tn_contract_batch.argtypes = [POINTER(c_void_p), POINTER(c_int64), POINTER(c_void_p), c_int32, c_void_p]
+_lib.tn_probe_mfma.argtypes = [c_int32, c_int64, c_void_p, POINTER(c_double), c_void_p]
+_lib.tn_probe_mfma_out_floats.restype = c_int64
+_lib.tn_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
 _lib.tn_amp_norm2.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_xeb.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_void_p, c_void_p]
@@ -104,7 +107,7 @@ _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_v
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
             "tn_contract_slices_checked", "tn_plan_shift_outputs", "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
-            "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
+            "tn_probe_mfma", "tn_probe_mfma_out_floats", "tn_probe_copy", "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
 
 
 def _check(rc: int):
@@ -402,3 +405,19 @@ def tn_amp_xeb(amp, n: int, idx, n_idx: int, out, stream=None):
 def tn_amp_hist(amp, n: int, scale: float, xmax: float, n_bins: int, counts, stream=None):
     _check(_lib.tn_amp_hist(c_void_p(_ptr(amp)), int(n), float(scale), float(xmax), int(n_bins),
                             c_void_p(_ptr(counts)), c_void_p(_stream(stream))))
+
+
+def tn_probe_mfma(kind: str, iters: int, out, stream=None) -> float:
+    """MFMA issue loop ('f32', 'f16' or 'bf16'); returns the flops issued."""
+    fl = c_double()
+    _check(_lib.tn_probe_mfma({"f32": 0, "f16": 1, "bf16": 2}[kind], int(iters), c_void_p(_ptr(out)), byref(fl),
+                              c_void_p(_stream(stream))))
+    return fl.value
+
+
+def tn_probe_mfma_out_floats() -> int:
+    return int(_lib.tn_probe_mfma_out_floats())
+
+
+def tn_probe_copy(src, dst, nbytes: int, stream=None):
+    _check(_lib.tn_probe_copy(c_void_p(_ptr(src)), c_void_p(_ptr(dst)), int(nbytes), c_void_p(_stream(stream))))

@@ -176,3 +176,21 @@ def test_cgemm_half(dtype, form, M, N, K, batch, splits):
     # the record is the largest |component| of the FP32 result before rounding
     comp_max = max(np.abs(C.real).max(), np.abs(C.imag).max())
     assert abs(mx.item() - comp_max) <= 2 * u * comp_max
+
+
+def test_probes_copy_and_mfma_loop():
+    """The ceiling probes: the streaming copy is exact (including a tail
+    shorter than one grid stride) and the MFMA loops run and report their
+    flop count."""
+    n = (1 << 20) + 48
+    src = torch.arange(n, dtype=torch.int32, device=DEV)
+    dst = torch.zeros_like(src)
+    tnrcs.tn_probe_copy(src, dst, n * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    out = torch.empty(tnrcs.tn_probe_mfma_out_floats(), dtype=torch.float32, device=DEV)
+    for kind, k in (("f32", 2), ("f16", 16), ("bf16", 16)):
+        fl = tnrcs.tn_probe_mfma(kind, 10, out)
+        torch.cuda.synchronize()
+        assert fl == 2.0 * 32 * 32 * k * 4 * 10 * (out.numel() // 64)
+        assert torch.isfinite(out).all()

@@ -122,7 +122,7 @@ def test_errors():
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "tnrcs.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(tn_\w+)\s*\(", header, flags=re.M))
+    declared = set(re.findall(r"^(?:int|int64_t|void|const char\*)\s+(tn_\w+)\s*\(", header, flags=re.M))
     assert len(declared) >= 15
     lib = ctypes.CDLL(tnrcs.LIB_PATH)
     for name in declared:
