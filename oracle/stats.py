@@ -45,3 +45,30 @@ def relative_error_norm(a, b) -> float:
     a = np.asarray(a, dtype=np.complex128).reshape(-1)
     b = np.asarray(b, dtype=np.complex128).reshape(-1)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def frugal_accept(amps, candidates, uniforms, scale: float, m: float) -> np.ndarray:
+    """Frugal rejection sampling over a bunch of amplitudes (main text: one
+    perfect sample is drawn from a bunch of 64 amplitudes by frugal sampling,
+    after the works it cites).  Candidate j, the amplitude amps[candidates[j]],
+    is accepted when u_j * m < scale * |a|^2, i.e. with probability
+    min(1, N p / m) for scale = N = 2^n and u_j uniform on [0, 1).  The
+    product and sum are taken in FP64 as written (re*re + im*im, then times
+    scale).  Returns the accepted amplitude indices in candidate order."""
+    cand = np.asarray(candidates, dtype=np.int64)
+    a = np.asarray(amps, dtype=np.complex128)[cand]
+    x = (a.real * a.real + a.imag * a.imag) * scale
+    keep = np.asarray(uniforms, dtype=np.float64) * m < x
+    return cand[keep]
+
+
+def frugal_acceptance_pt(m: float) -> float:
+    """Acceptance probability of one candidate when N p follows the
+    Porter-Thomas law Exp(1): E[min(1, x/m)] = (1 - e^-m) / m."""
+    return float(-np.expm1(-m) / m)
+
+
+def frugal_accepted_mean_pt(m: float) -> float:
+    """Mean of x = N p over accepted candidates under Porter-Thomas:
+    E[x min(x, m)] / E[min(x, m)] = (2 - (m + 2) e^-m) / (1 - e^-m)."""
+    return float((2.0 - (m + 2.0) * np.exp(-m)) / -np.expm1(-m))
