@@ -339,6 +339,28 @@ def crosscheck_30q(tnrcs, torch, np):
             se = float(np.sqrt(max(N * N * s2 / m - (f + 1.0) ** 2, 0.0) / m))
             r[name] = {"amp_rel_err": err, "xeb": f, "xeb_fp64": float(g[f"xeb_{name}"]),
                        "abs_delta_xeb": abs(f - float(g[f"xeb_{name}"])), "xeb_stderr": se}
+        if dtype == "c64":
+            # frugal rejection sampling over 1e5 random bunches of 64 amplitudes (M = 10)
+            rng = np.random.default_rng(9)
+            starts = rng.integers(0, N // 64, size=100_000) * 64
+            cand = torch.from_numpy((starts[:, None] + np.arange(64)[None, :]).reshape(-1)).cuda()
+            u = torch.from_numpy(rng.random(cand.numel())).cuda()
+            kept = torch.empty(cand.numel(), dtype=torch.int64, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            e0.record()
+            tnrcs.tn_amp_frugal(amp, N, cand, cand.numel(), u, float(N), 10.0, kept, cnt)
+            e1.record()
+            torch.cuda.synchronize()
+            k = int(cnt.item())
+            acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+            tnrcs.tn_amp_xeb(amp, N, kept[:k], k, acc)
+            s1, s2 = acc.cpu().numpy()
+            f = N * s1 / k - 1.0
+            se = float(np.sqrt(max(N * N * s2 / k - (f + 1.0) ** 2, 0.0) / k))
+            r["frugal"] = {"bunches": 100_000, "m": 10.0, "kept": k, "acceptance": k / cand.numel(),
+                           "xeb_of_kept": f, "xeb_stderr": se, "kernel_ms": e0.elapsed_time(e1)}
+            log(f"[bench] 30q frugal sampling: {k} bit strings kept of {cand.numel()} candidates "
+                f"({k / cand.numel():.4f}), their XEB {f:.4f} +- {se:.4f}")
         out[dtype] = r
         log(f"[bench] 30q all-open {dtype}: {sec:.3f} s, amplitude error ideal {r['ideal']['amp_rel_err']:.2e} "
             f"uniform {r['uniform']['amp_rel_err']:.2e}, XEB ideal {r['ideal']['xeb']:.5f} (FP64 "

@@ -330,6 +330,18 @@ int tn_amp_norm2(const void* amp, int64_t n, void* out_dev, void* stream);
  *  out[1] = sum_i |a[idx_i]|^4 (idx: device int64[n_idx]).  F = 2^n out[0]/n_idx - 1. */
 int tn_amp_xeb(const void* amp, int64_t n, const void* idx_dev, int64_t n_idx, void* out_dev,
                void* stream);
+/*  Frugal rejection sampling (main text: one perfect sample from a bunch of
+ *  64 amplitudes by frugal sampling, after the works it cites): candidate j,
+ *  the amplitude a[idx[j]] (idx_dev may be NULL: candidate j is a[j]), is
+ *  kept when u[j] * m < scale * (re*re + im*im), evaluated in FP64 with each
+ *  operation rounded separately; with scale = N = 2^n and u uniform on
+ *  [0, 1) that is probability min(1, N p / m).  u_dev: device double[n_cand]
+ *  (the caller draws the random numbers); kept amplitude indices go to
+ *  out_idx_dev (device int64[n_cand]) in unspecified order, their number to
+ *  *count_dev (device int64).  Candidates outside [0, n) are never kept.
+ *  scale, m > 0. */
+int tn_amp_frugal(const void* amp, int64_t n, const void* idx_dev, int64_t n_cand, const void* u_dev, double scale,
+                  double m, void* out_idx_dev, void* count_dev, void* stream);
 /*  Histogram of x = scale * |a|^2 into n_bins bins of width xmax/n_bins
  *  (last bin collects x >= xmax), counts as uint64 (Eq. (fxeb) check). */
 int tn_amp_hist(const void* amp, int64_t n, double scale, double xmax, int32_t n_bins,

@@ -993,6 +993,17 @@ int tn_amp_xeb(const void* amp, int64_t n, const void* idx_dev, int64_t n_idx, v
   return TN_OK;
 }
 
+int tn_amp_frugal(const void* amp, int64_t n, const void* idx_dev, int64_t n_cand, const void* u_dev, double scale,
+                  double m, void* out_idx_dev, void* count_dev, void* stream) {
+  if (!amp || n < 0 || n_cand < 0 || (n_cand > 0 && (!u_dev || !out_idx_dev)) || !count_dev)
+    return fail(TN_E_ARG, "bad argument");
+  if (!(m > 0) || !(scale > 0)) return fail(TN_E_ARG, "scale and m must be positive");
+  hipError_t e = launch_frugal((const double*)amp, n, (const int64_t*)idx_dev, n_cand, (const double*)u_dev, scale, m,
+                               (int64_t*)out_idx_dev, (unsigned long long*)count_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "frugal sampling kernel");
+  return TN_OK;
+}
+
 int tn_amp_hist(const void* amp, int64_t n, double scale, double xmax, int32_t n_bins, void* counts_dev,
                 void* stream) {
   if (!amp || !counts_dev || n < 0 || n_bins < 1 || !(xmax > 0)) return fail(TN_E_ARG, "bad argument");

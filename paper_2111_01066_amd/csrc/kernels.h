@@ -49,6 +49,8 @@ int64_t splitk_blocks(const IndexOp& op);
 // sliced_factors, by the per-slice factor that the bind kernel left in ctrl.
 hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,
                         const float* out_scales, int n_slots, bool sliced_factors, hipStream_t s);
+hipError_t launch_frugal(const double* amp, int64_t n, const int64_t* idx, int64_t n_cand, const double* u,
+                         double scale, double m, int64_t* out, unsigned long long* count, hipStream_t s);
 hipError_t launch_norm2(const double* amp, int64_t n, double* out, hipStream_t s);
 hipError_t launch_xeb(const double* amp, int64_t n, const int64_t* idx, int64_t n_idx, double* out,
                       hipStream_t s);

@@ -648,6 +648,43 @@ hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* c
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- frugal --
+// Frugal rejection sampling: candidate j (amplitude idx[j], or j) is kept
+// when u[j] * m < scale * (re*re + im*im), evaluated in FP64 with every
+// operation rounded on its own (no fused multiply-add), so the decision is
+// the same as a plain FP64 evaluation of that expression.  Kept indices are
+// appended through an atomic counter (order unspecified).
+
+__global__ void k_zero_count(unsigned long long* count) { *count = 0ull; }
+
+__global__ __launch_bounds__(256) void k_frugal(const double* __restrict__ amp, int64_t n,
+                                               const int64_t* __restrict__ idx, int64_t n_cand,
+                                               const double* __restrict__ u, double scale, double m,
+                                               int64_t* __restrict__ out, unsigned long long* count) {
+#pragma clang fp contract(off)
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_cand;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx ? idx[j] : j;
+    if (i < 0 || i >= n) continue;  // out-of-range candidates are never kept
+    const double re = amp[2 * i], im = amp[2 * i + 1];
+    const double rr = re * re;
+    const double ii = im * im;
+    const double x = (rr + ii) * scale;
+    const double t = u[j] * m;
+    if (t < x) out[atomicAdd(count, 1ull)] = i;
+  }
+}
+
+hipError_t launch_frugal(const double* amp, int64_t n, const int64_t* idx, int64_t n_cand, const double* u,
+                         double scale, double m, int64_t* out, unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, count);
+  if (n_cand > 0) {
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_cand + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_frugal, dim3((unsigned)grid), dim3(256), 0, s, amp, n, idx, n_cand, u, scale, m, out, count);
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- reductions --
 // Deterministic two-pass FP64 sums: fixed grid of per-block partials, then
 // one block sums the partials in a fixed order.

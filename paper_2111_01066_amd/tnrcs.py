@@ -100,6 +100,8 @@ _lib.tn_contract_batch.argtypes = [POINTER(c_void_p), POINTER(c_int64), POINTER(
 _lib.tn_probe_mfma.argtypes = [c_int32, c_int64, c_void_p, POINTER(c_double), c_void_p]
 _lib.tn_probe_mfma_out_floats.restype = c_int64
 _lib.tn_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
+_lib.tn_amp_frugal.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_double, c_double, c_void_p,
+                               c_void_p, c_void_p]
 _lib.tn_amp_norm2.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_xeb.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]
 _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_void_p, c_void_p]
@@ -107,7 +109,7 @@ _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_v
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
             "tn_contract_slices_checked", "tn_plan_shift_outputs", "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
-            "tn_probe_mfma", "tn_probe_mfma_out_floats", "tn_probe_copy", "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_hist"]
+            "tn_probe_mfma", "tn_probe_mfma_out_floats", "tn_probe_copy", "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_frugal", "tn_amp_hist"]
 
 
 def _check(rc: int):
@@ -421,3 +423,10 @@ def tn_probe_mfma_out_floats() -> int:
 
 def tn_probe_copy(src, dst, nbytes: int, stream=None):
     _check(_lib.tn_probe_copy(c_void_p(_ptr(src)), c_void_p(_ptr(dst)), int(nbytes), c_void_p(_stream(stream))))
+
+
+def tn_amp_frugal(amp, n: int, idx, n_cand: int, u, scale: float, m: float, out_idx, count, stream=None):
+    """Frugal rejection sampling (see include/tnrcs.h); idx may be None."""
+    _check(_lib.tn_amp_frugal(c_void_p(_ptr(amp)), int(n), None if idx is None else c_void_p(_ptr(idx)),
+                              int(n_cand), c_void_p(_ptr(u)), float(scale), float(m), c_void_p(_ptr(out_idx)),
+                              c_void_p(_ptr(count)), c_void_p(_stream(stream))))

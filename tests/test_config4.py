@@ -68,5 +68,23 @@ def test_config4_30q_all_open_vs_statevector(golden, dtype):
         assert err < TOL[dtype], (name, err)
         # equal XEB error: the estimate moves by less than one standard error
         assert abs(f - ref) < se, (name, f, ref, se)
+    if dtype == "c64":
+        # frugal rejection sampling over 2^14 random bunches of 64 (the 6
+        # lowest qubits open): the kept bit strings' N <p> - 1 is that of
+        # Porter-Thomas reweighted by min(1, N p / M)
+        from oracle.stats import frugal_accepted_mean_pt
+        rng = np.random.default_rng(9)
+        starts = rng.integers(0, N // 64, size=1 << 14) * 64
+        cand = torch.from_numpy((starts[:, None] + np.arange(64)[None, :]).reshape(-1)).cuda()
+        u = torch.from_numpy(rng.random(cand.numel())).cuda()
+        out = torch.empty(cand.numel(), dtype=torch.int64, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        tnrcs.tn_amp_frugal(amp, N, cand, cand.numel(), u, float(N), 10.0, out, cnt)
+        kept = out[: int(cnt.item())]
+        f, se = _xeb(amp, kept)
+        want = frugal_accepted_mean_pt(10.0) - 1.0
+        print(f"  frugal sampling: {kept.numel()} kept of {cand.numel()}, XEB {f:.4f} (expected {want:.4f}, "
+              f"s.e. {se:.4f})", flush=True)
+        assert abs(f - want) < 4 * se
     del amp
     torch.cuda.empty_cache()
