@@ -127,7 +127,8 @@ __device__ __forceinline__ int lds_pad(int e) {
   return e + (e >> 5) * G;
 }
 
-// Tile of 2^TB elements, 256 threads, 2^TB / 256 elements per thread.  All of
+// Tile of 2^TB elements (up to 2^12 complex64 or 2^13 four-byte elements,
+// 32 KB either way), 256 threads, 2^TB / 256 elements per thread.  All of
 // a thread's loads are issued before any LDS store so they are in flight
 // together; the writes are streaming (non-temporal) stores.  The parts of
 // the offsets that depend only on the unrolled iteration are tabulated once
@@ -200,8 +201,11 @@ static void launch_perm_tb(int tb, dim3 g, const E* in, E* out, const PermArgs& 
     case 11:
       hipLaunchKernelGGL((k_permute<11, E>), g, dim3(kPermThreads), 0, s, in, out, A);
       break;
-    default:
+    case 12:
       hipLaunchKernelGGL((k_permute<12, E>), g, dim3(kPermThreads), 0, s, in, out, A);
+      break;
+    default:
+      if constexpr (sizeof(E) == 4) hipLaunchKernelGGL((k_permute<13, E>), g, dim3(kPermThreads), 0, s, in, out, A);
       break;
   }
 }
@@ -237,7 +241,7 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
   // choose the tile: grow input-fast and output-fast bit sets alternately
   std::vector<bool> inT(rank, false);
   int tb = 0, a = 0, b = 0;
-  const int cap = std::min(kPermTileBits, rank);
+  const int cap = std::min(elem_bytes == 4 ? kPermTileBits + 1 : kPermTileBits, rank);
   while (tb < cap) {
     bool grew = false;
     if (a < rank && (a <= b || b >= rank)) {
@@ -273,7 +277,7 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
   if (!make_runs(p1, &A.in_tile) || !make_runs(p2, &A.out_tile) || !make_runs(p3, &A.f2e) ||
       !make_runs(p4, &A.id_in) || !make_runs(p5, &A.id_out))
     return hipErrorInvalidValue;
-  if (A.tbits < 10 || A.tbits > kPermTileBits) return hipErrorInvalidValue;
+  if (A.tbits < 10 || A.tbits > (elem_bytes == 4 ? kPermTileBits + 1 : kPermTileBits)) return hipErrorInvalidValue;
   const int64_t grid = std::min<int64_t>(A.n_tiles, 16384);
   const dim3 g((unsigned)grid, (unsigned)batch);
   if (elem_bytes == 8)

@@ -130,17 +130,23 @@ def _from_pairs(t):
     return x[..., 0] + 1j * x[..., 1]
 
 
-@pytest.mark.parametrize("rank", [3, 9, 14, 21])
+@pytest.mark.parametrize("rank", [3, 9, 12, 13, 14, 16, 21, 24])
 def test_permute_4byte_bit_exact(rank):
+    """Four-byte elements (FP16/BF16 pairs), tiles of up to 2^13 elements."""
     rng = np.random.default_rng(100 + rank)
-    perm = rng.permutation(rank).tolist()
     x = rng.integers(0, 2**31, size=(3, 1 << rank), dtype=np.int64).astype(np.int32)
     xin = torch.from_numpy(x).to(DEV)
-    out = torch.empty_like(xin)
-    print(f"permute 4-byte rank={rank}", flush=True)
-    tnrcs.tn_permute(xin, out, perm, batch=3, elem_bytes=4)
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
+    for trial in range(3):
+        perm = rng.permutation(rank).tolist()
+        if trial == 1:
+            perm = list(range(rank))[::-1]
+        if trial == 2:
+            perm = list(range(rank // 2, rank)) + list(range(rank // 2))
+        out = torch.empty_like(xin)
+        print(f"permute 4-byte rank={rank} trial={trial}", flush=True)
+        tnrcs.tn_permute(xin, out, perm, batch=3, elem_bytes=4)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
 
 
 @pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
