@@ -89,8 +89,9 @@ typedef struct {
   int32_t device;         /* HIP device ordinal */
   int32_t host_fold_log2; /* steps whose result has at most 2^host_fold_log2 entries and whose operands
                              are leaves or folded leaves are evaluated once on the host in FP64 */
-  int32_t tune;           /* 1: at tn_plan time, time every dense GEMM step's tile size (64 or 128)
-                             and K-split count on the device and keep the fastest (see below) */
+  int32_t tune;           /* 1: at tn_plan time, choose each step's kernel class (permutes + GEMM or a
+                             fused kernel) and every dense GEMM step's tile size (64 or 128) and
+                             K-split count by timing them on the device (see below) */
   int64_t arena_bytes;    /* arena == NULL: device memory budget for intermediates (0: 92% of free
                              memory); arena != NULL: the size of that workspace in bytes */
   void* arena;            /* NULL: the plan allocates and owns its intermediate arena.  Otherwise a
@@ -136,13 +137,24 @@ typedef struct {
  * (the format's maximum reached) or TN_FLAG_UNDERFLOW (a step's largest
  * magnitude fell below 2^-2), read with tn_plan_status.
  *
- * Tuning (opts->tune): for each distinct dense-GEMM shape of the plan
- * (dtype, M, N, K, form) every valid tile size and K-split count is timed
- * with HIP events on the plan's own buffers (the arena is zero-filled first)
- * and the fastest kept; results are cached per process and, with tune_db, in
- * a file.  The split count changes the summation order inside a GEMM, so two
- * processes that tune differently may differ in the last bits; a shared
- * tune_db file makes the choice reproducible. */
+ * Tuning (opts->tune), two stages.  Kernel class: a step with more than
+ * one valid kernel class (permutes + MFMA GEMM against the fused gathered
+ * kernel when the contraction has at most 2^6 terms; gathered, skewed and
+ * split-K against each other for steps with too few outputs for the GEMM)
+ * is run in each on a one-step plan of the same operand layouts over
+ * zero-filled scratch buffers (at most a third of the free device memory;
+ * larger steps keep the default rule), and the fastest is planned.  Tile:
+ * for each distinct dense-GEMM shape of the plan (dtype, M, N, K, form)
+ * every valid tile size and K-split count is timed with HIP events on the
+ * plan's own buffers (the arena is zero-filled first) and the fastest kept.
+ * Results are cached per process and, with tune_db, in a file (lines
+ * "tnrcs-class dtype key class ms" and "tnrcs-gemm dtype M N K form cap tile
+ * split occ ms"; the key is the step's operand and result layouts with the
+ * wires relabelled, as in tn_plan_json's "steps").  A dry-run plan with tune
+ * set measures nothing but applies the class lines already cached or in
+ * tune_db.  The split count and the class change the summation order inside
+ * a step, so two processes that tune differently may differ in the last
+ * bits; a shared tune_db file makes the choice reproducible. */
 void tn_plan_opts_default(tn_plan_opts* o);
 
 /* Plans the contraction (main text TNC section; Supplement Fig. S2 and the
@@ -220,7 +232,9 @@ int tn_contract_batch(const tn_plan_t* plans, const int64_t* ranges, void* const
 int tn_plan_info(tn_plan_t p, tn_plan_stats* s);
 
 /* Writes the plan as JSON (host folds, device leaves, per-step kernels with
- * layouts and arena offsets) into buf (capacity cap bytes, NUL-terminated);
+ * layouts and arena offsets, and per device step its extents nM nN nK, its
+ * kernel class (1 GEMM, 2 gathered, 3 skewed, 4 split-K), its
+ * relabelled layout key and whether the class tuner chose it) into buf (capacity cap bytes, NUL-terminated);
  * *needed receives the full length + 1.  buf may be NULL to query the size. */
 int tn_plan_json(tn_plan_t p, char* buf, int64_t cap, int64_t* needed);
 

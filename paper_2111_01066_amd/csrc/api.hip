@@ -340,6 +340,147 @@ static int tune_plan(tn_plan_s* p) {
   return TN_OK;
 }
 
+// Kernel-class autotuning (the permute/GEMM fusion choice).  A step whose
+// shape admits more than one kernel class is run in each candidate class on
+// a one-step plan with the same operand layouts over zero-filled buffers of
+// its own; the fastest class overrides the planner's rule.  Candidates: the
+// gathered kernel against permutes + GEMM when the contraction is short
+// (2^nK <= 2^kFuseMaxK terms), and gathered, split-K and skewed against each
+// other for steps too narrow for the GEMM.  Steps whose buffers would exceed
+// the tuning budget (a third of the free device memory, at most
+// kClassTuneMaxBytes) keep the rule.  Choices are cached per process and in
+// the tuning database by dtype and the step's relabelled layouts.
+constexpr int kFuseMaxK = 6;
+constexpr int64_t kClassTuneMaxBytes = (int64_t)64 << 30;
+
+// Average time of one run of a one-step plan's ops in class `cls` (INFINITY
+// when the step does not fit the budget); builds, runs and frees the plan.
+static int time_class(const PlanCore& P, const std::vector<int>& a, const std::vector<int>& b,
+                      const std::vector<int>& c, int cls, int64_t budget, float* ms) {
+  *ms = INFINITY;
+  tn_plan_s q;
+  PlanCore& Q = q.core;
+  Q.pair_a = a;
+  Q.pair_b = b;
+  Q.pair_out = c;
+  Q.opts = P.opts;
+  Q.opts.tune = 0;
+  Q.opts.arena = nullptr;
+  Q.opts.arena_bytes = 0;
+  Q.class_override[0] = cls;
+  std::string err;
+  int rc = build_pair_plan(Q, err);
+  if (rc) return fail(rc, "class tuner: " + err);
+  if (Q.steps.size() != 1 || Q.steps[0].cls != cls) return fail(TN_E_UNSUPPORTED, "class tuner: class not applied");
+  q.eb = elem_bytes_of(Q.opts.dtype);
+  q.device = P.opts.device;
+  const int64_t na = (int64_t)1 << a.size(), nb = (int64_t)1 << b.size(), nc = (int64_t)1 << c.size();
+  const int64_t bytes = (na + nb + nc + Q.arena_elems) * q.eb;
+  if (bytes > budget) return TN_OK;
+  char *A = nullptr, *B = nullptr, *C = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    hipFree(A);
+    hipFree(B);
+    hipFree(C);
+    hipFree(q.d_arena);
+    hipFree(q.d_maxslots);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  hipError_t e = hipSuccess;
+  const std::pair<char**, int64_t> bufs[] = {{&A, na}, {&B, nb}, {&C, nc}, {&q.d_arena, Q.arena_elems}};
+  for (const auto& [ptr, n] : bufs)
+    if (e == hipSuccess && (e = hipMalloc((void**)ptr, (size_t)std::max<int64_t>(n * q.eb, 256))) == hipSuccess)
+      e = hipMemset(*ptr, 0, (size_t)std::max<int64_t>(n * q.eb, 256));
+  if (e == hipSuccess) e = hipMalloc((void**)&q.d_maxslots, (size_t)std::max(Q.n_slots, 1) * 4);
+  if (e == hipSuccess) e = hipMemset(q.d_maxslots, 0, (size_t)std::max(Q.n_slots, 1) * 4);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "class tuner: allocate");
+  }
+  q.ext_a = A;
+  q.ext_b = B;
+  q.ext_c = C;
+  // the GEMM of the dense class runs its own tuned variant
+  for (Op& op : Q.ops)
+    if (op.kind == kOpGemm && (rc = tune_gemm(Q.opts.dtype, op.gemm, resolve(&q, op.a), resolve(&q, op.b),
+                                                resolve(&q, op.c),
+                                                op.gemm.split_max > 1 ? (float2*)resolve(&q, op.w) : nullptr,
+                                                op.max_slot >= 0 ? q.d_maxslots + op.max_slot : nullptr,
+                                                P.opts.tune_db, err))) {
+      cleanup();
+      return fail(rc, err);
+    }
+  auto run = [&](int reps, float* out) -> int {
+    HIP_TRY(hipEventRecord(e0, nullptr), "class tuner: event");
+    for (int r = 0; r < reps; ++r)
+      for (const Op& op : Q.ops) {
+        int rc2 = launch_op(&q, op, nullptr);
+        if (rc2) return rc2;
+      }
+    HIP_TRY(hipEventRecord(e1, nullptr), "class tuner: event");
+    HIP_TRY(hipEventSynchronize(e1), "class tuner: synchronize");
+    HIP_TRY(hipEventElapsedTime(out, e0, e1), "class tuner: elapsed time");
+    return TN_OK;
+  };
+  float t1 = 0.f, tr = 0.f;
+  rc = run(1, &t1);
+  // repeat to about 2 ms of work (at most 20 runs)
+  const int reps = std::max(1, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
+  if (!rc) rc = run(reps, &tr);
+  cleanup();
+  if (!rc) *ms = tr / reps;
+  return rc;
+}
+
+// measure = false (plans without device state): only the choices already in
+// the process cache or the database apply.
+static int tune_classes(PlanCore& P, bool measure) {
+  size_t free_b = 0, total_b = 0;
+  if (measure) HIP_TRY(hipMemGetInfo(&free_b, &total_b), "class tuner: hipMemGetInfo");
+  const int64_t budget = std::min<int64_t>((int64_t)(free_b / 3), kClassTuneMaxBytes);
+  bool changed = false;
+  for (const PlanCore::StepInfo& st : P.steps) {
+    const unsigned valid = step_classes(st.nM, st.nN, st.nK);
+    std::vector<int> cand;
+    if (valid & (1u << kOpGemm)) {
+      if (st.nK > kFuseMaxK) continue;
+      cand = {kOpGemm, kOpGeneric};
+    } else {
+      for (int k : {kOpGeneric, kOpSplitK, kOpSkinny})
+        if (valid & (1u << k)) cand.push_back(k);
+      if (cand.size() < 2) continue;
+    }
+    const std::string& key = st.key;
+    int best = -1;
+    if (!class_lookup(P.opts.dtype, key, P.opts.tune_db, &best)) {
+      if (!measure) continue;
+      float best_ms = INFINITY;
+      for (int k : cand) {
+        float ms = INFINITY;
+        int rc = time_class(P, st.la, st.lb, st.lc, k, budget, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = k;
+        }
+      }
+      if (best < 0) continue;  // above the tuning budget: the rule stands
+      class_store(P.opts.dtype, key, P.opts.tune_db, best, best_ms);
+    }
+    if (!(valid & (1u << best))) continue;
+    P.class_override[st.t] = best;
+    changed |= best != st.cls;
+  }
+  if (!changed) return TN_OK;
+  std::string err;
+  int rc = build_plan(P, err);
+  return rc ? fail(rc, "rebuild after class tuning: " + err) : TN_OK;
+}
+
 static void drop_graph(tn_plan_s* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
@@ -435,6 +576,10 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   p->device = o.device;
   p->eb = elem_bytes_of(o.dtype);
   if (o.dry_run) {
+    if (o.tune && (rc = tune_classes(P, false))) {
+      delete p;
+      return rc;
+    }
     if (o.dtype != TN_DTYPE_C64) leaf_exponents(P);
     propagate_exponents(P);
     *out = p;
@@ -448,6 +593,7 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps, co
   };
   hipError_t e = hipSetDevice(o.device);
   if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
+  if (o.tune && (rc = tune_classes(P, true))) return bail(rc);
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) return bail(hip_fail(e, "hipMemGetInfo"));

@@ -4,6 +4,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,20 @@ struct PlanCore {
   tn_plan_stats stats{};
   std::string json;
 
+  // kernel class per device step: the planner's rule unless the autotuner
+  // measured another valid class to be faster (step -> OpKind)
+  std::map<int, int> class_override;
+  struct StepInfo {
+    int32_t t = 0;
+    // operand and result layouts, most significant first, with the wires
+    // relabelled by first appearance (A's, then B's new ones): steps with
+    // the same labels run the same kernels on the same index maps
+    std::vector<int> la, lb, lc;
+    std::string key;  // the three label lists as text ("0.1.2/3.1/0.2.3")
+    int32_t nM = 0, nN = 0, nK = 0, cls = 0;
+  };
+  std::vector<StepInfo> steps;  // device steps as planned
+
   // pairwise-contraction mode (one step A x B -> C over caller buffers)
   bool pair_mode = false;
   std::vector<int> pair_a, pair_b, pair_out;  // index labels, most significant first
@@ -162,6 +177,27 @@ int build_pair_plan(PlanCore& P, std::string& err);
 // (Re)writes P.json from the current plan.
 void make_json(PlanCore& P);
 
+// Kernel classes of a step with 2^nM x 2^nN outputs over 2^nK terms.  dense
+// (permutes + MFMA GEMM): both free extents at least 64 (the smallest GEMM
+// tile) and K at least 16; split-K: at most 64 outputs; skewed (Supplement,
+// CPU-architecture section): the small operand fits in LDS, few outputs per
+// row of the large one; gathered: always valid.  Bit mask over OpKind.
+inline unsigned step_classes(int nM, int nN, int nK) {
+  unsigned m = 1u << kOpGeneric;
+  if (nM >= 6 && nN >= 6 && nK >= 4) m |= 1u << kOpGemm;
+  if (nM + nN <= 6 && nK >= 4) m |= 1u << kOpSplitK;
+  if (nN <= 4 && nK + nN <= kSkinnyMaxLog2 && nM >= 8) m |= 1u << kOpSkinny;
+  return m;
+}
+// The planner's rule among them: dense where valid, split-K for long sums
+// into few outputs, then skewed, then gathered.
+inline int default_class(int nM, int nN, int nK) {
+  const unsigned m = step_classes(nM, nN, nK);
+  if (m & (1u << kOpGemm)) return kOpGemm;
+  if ((m & (1u << kOpSplitK)) && nK >= 10) return kOpSplitK;
+  if (m & (1u << kOpSkinny)) return kOpSkinny;
+  return kOpGeneric;
+}
 // Planner entry (host only).  Returns TN_OK or an error code with a message.
 int build_plan(PlanCore& P, std::string& err);
 // Blocks of the split-K reduction over 2^nK terms (its workspace holds

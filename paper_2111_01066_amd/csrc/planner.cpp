@@ -294,6 +294,12 @@ void make_json(PlanCore& P) {
     }
     js << "}";
   }
+  js << "],\"steps\":[";
+  for (size_t i = 0; i < P.steps.size(); ++i) {
+    const PlanCore::StepInfo& st = P.steps[i];
+    js << (i ? "," : "") << "{\"t\":" << st.t << ",\"nM\":" << st.nM << ",\"nN\":" << st.nN << ",\"nK\":" << st.nK
+       << ",\"cls\":" << st.cls << ",\"key\":\"" << st.key << "\",\"tuned\":" << (P.class_override.count(st.t) ? "true" : "false") << "}";
+  }
   js << "],\"accum\":{\"n_open\":" << P.accum.n_open << ",\"root\":";
   json_ref(js, P.accum.root);
   js << ",\"y2root\":";
@@ -343,6 +349,30 @@ static int build_pair_network(PlanCore& P, std::vector<HostTensor>& leaves, std:
   P.pairs = {0, 1};
   P.sliced.clear();
   return TN_OK;
+}
+
+static PlanCore::StepInfo step_info(int t, const std::vector<int>& La, const std::vector<int>& Lb,
+                                    const std::vector<int>& Lc, int nM, int nN, int nK, int cls) {
+  PlanCore::StepInfo st;
+  st.t = t;
+  st.nM = nM;
+  st.nN = nN;
+  st.nK = nK;
+  st.cls = cls;
+  std::map<int, int> lab;
+  auto relabel = [&](const std::vector<int>& in, std::vector<int>& out) {
+    for (int w : in) {
+      auto it = lab.find(w);
+      if (it == lab.end()) it = lab.emplace(w, (int)lab.size()).first;
+      out.push_back(it->second);
+    }
+    if (!st.key.empty()) st.key += '/';
+    for (size_t i = 0; i < out.size(); ++i) st.key += (i ? "." : "") + std::to_string(out[i]);
+  };
+  relabel(La, st.la);
+  relabel(Lb, st.lb);
+  relabel(Lc, st.lc);
+  return st;
 }
 
 int build_plan(PlanCore& P, std::string& err) {
@@ -523,6 +553,7 @@ int build_plan(PlanCore& P, std::string& err) {
       where[d.ssa] = TRef{kLeaves, d.stored_off};
   }
   P.ops.clear();
+  P.steps.clear();
   P.n_slots = 0;
   std::vector<Buf> bufs;
   std::vector<int> buf_of_ssa(L + S, -1);
@@ -578,9 +609,17 @@ int build_plan(PlanCore& P, std::string& err) {
     const bool half = P.opts.dtype != TN_DTYPE_C64;
     const double eb = elem_bytes_plan(P);
     const int64_t f2 = 8 / (int64_t)eb;  // plan elements per float2 workspace entry
-    // dense: both free extents at least 64 (the smallest GEMM tile) and K at least 16
-    const bool dense = nM >= 6 && nN >= 6 && nK >= 4;
-    if (dense) {
+    // kernel class: the planner's rule, unless the class autotuner measured
+    // another valid class to be faster for this step
+    const unsigned valid = step_classes(nM, nN, nK);
+    int cls = default_class(nM, nN, nK);
+    {
+      auto ov = P.class_override.find(t);
+      if (ov != P.class_override.end() && ov->second >= 0 && ov->second < 32 && (valid & (1u << ov->second)))
+        cls = ov->second;
+    }
+    P.steps.push_back(step_info(t, La, Lb, Lc, nM, nN, nK, cls));
+    if (cls == kOpGemm) {
       // K order: keep whichever operand already has K as its lowest block
       auto k_low_block = [&](const std::vector<int>& Lx2, std::vector<int>& kord) {
         int r = (int)Lx2.size();
@@ -681,11 +720,9 @@ int build_plan(PlanCore& P, std::string& err) {
       P.stats.n_dense++;
     } else {
       Op g;
-      const bool splitk = (nM + nN) <= 6 && nK >= 10;
-      // skewed (Supplement, CPU-architecture section): the small operand
-      // fits in LDS, few outputs per row of the large one
-      const bool skinny = !splitk && nN <= 4 && nK + nN <= kSkinnyMaxLog2 && nM >= 8;
-      g.kind = splitk ? kOpSplitK : (skinny ? kOpSkinny : kOpGeneric);
+      const bool splitk = cls == kOpSplitK;
+      const bool skinny = cls == kOpSkinny;
+      g.kind = cls;
       g.step = t;
       g.idx.nM = nM;
       g.idx.nN = nN;

@@ -16,4 +16,10 @@ namespace tnrcs {
 int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float2* w, float* slot, const char* db,
               std::string& err);
 
+// Kernel-class choices of whole steps, keyed by dtype and a canonical
+// description of the step's operand layouts: lookup (process cache, then the
+// database file db if given) and store (both).
+bool class_lookup(int dtype, const std::string& key, const char* db, int* cls);
+void class_store(int dtype, const std::string& key, const char* db, int cls, float ms);
+
 }  // namespace tnrcs

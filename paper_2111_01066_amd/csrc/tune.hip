@@ -4,6 +4,8 @@
 // capacity) and, when a database path is given, in a plain text file
 // ("tnrcs-gemm dtype M N K form cap tile split occ ms" per line; occ is the
 // waves-per-SIMD variant of the FP16/BF16 128x128 kernel, 0 elsewhere).
+// The same file holds the kernel-class choices of whole steps
+// ("tnrcs-class dtype key class ms"), which the plan builder times itself.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,22 +35,31 @@ struct Choice {
 std::mutex g_mu;
 std::map<Key, Choice> g_cache;
 std::map<std::string, std::set<Key>> g_db_keys;  // keys present in each database file
+std::map<std::pair<int, std::string>, int> g_class;  // (dtype, step key) -> kernel class
+std::map<std::string, std::set<std::pair<int, std::string>>> g_db_class;
 
 void load_db(const std::string& path) {
   if (g_db_keys.count(path)) return;
   std::set<Key>& have = g_db_keys[path];
+  std::set<std::pair<int, std::string>>& have_c = g_db_class[path];
   FILE* f = std::fopen(path.c_str(), "r");
   if (!f) return;
-  char tag[32];
-  int dt, form, cap, tile, split, occ;
-  long long M, N, K;
-  float ms;
-  while (std::fscanf(f, "%31s %d %lld %lld %lld %d %d %d %d %d %f", tag, &dt, &M, &N, &K, &form, &cap, &tile, &split,
-                     &occ, &ms) == 11) {
-    if (std::string(tag) != "tnrcs-gemm") continue;
-    const Key k{dt, M, N, K, form, cap};
-    g_cache[k] = Choice{tile, split, occ, ms};
-    have.insert(k);
+  char line[4096], tag[32], key[4000];
+  while (std::fgets(line, sizeof line, f)) {
+    int dt, form, cap, tile, split, occ, cls;
+    long long M, N, K;
+    float ms;
+    if (std::sscanf(line, "%31s", tag) != 1) continue;
+    const std::string t(tag);
+    if (t == "tnrcs-gemm" && std::sscanf(line, "%31s %d %lld %lld %lld %d %d %d %d %d %f", tag, &dt, &M, &N, &K, &form,
+                                         &cap, &tile, &split, &occ, &ms) == 11) {
+      const Key k{dt, M, N, K, form, cap};
+      g_cache[k] = Choice{tile, split, occ, ms};
+      have.insert(k);
+    } else if (t == "tnrcs-class" && std::sscanf(line, "%31s %d %3999s %d %f", tag, &dt, key, &cls, &ms) == 5) {
+      g_class[{dt, std::string(key)}] = cls;
+      have_c.insert({dt, std::string(key)});
+    }
   }
   std::fclose(f);
 }
@@ -148,6 +159,33 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
   g_cache[key] = best;
   if (db) append_db(db, key, best);
   return TN_OK;
+}
+
+bool class_lookup(int dtype, const std::string& key, const char* db, int* cls) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (db) load_db(db);
+  auto it = g_class.find({dtype, key});
+  if (it == g_class.end()) return false;
+  *cls = it->second;
+  if (db && g_db_class[db].insert({dtype, key}).second) {  // chosen earlier in this process
+    if (FILE* f = std::fopen(db, "a")) {
+      std::fprintf(f, "tnrcs-class %d %s %d %.5f\n", dtype, key.c_str(), *cls, 0.f);
+      std::fclose(f);
+    }
+  }
+  return true;
+}
+
+void class_store(int dtype, const std::string& key, const char* db, int cls, float ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_class[{dtype, key}] = cls;
+  if (!db) return;
+  load_db(db);
+  if (!g_db_class[db].insert({dtype, key}).second) return;
+  if (FILE* f = std::fopen(db, "a")) {
+    std::fprintf(f, "tnrcs-class %d %s %d %.5f\n", dtype, key.c_str(), cls, ms);
+    std::fclose(f);
+  }
 }
 
 }  // namespace tnrcs

@@ -163,7 +163,16 @@ def test_tuned_plan_vs_oracle_and_cache(tmp_path, dtype):
     assert gemms and all(o["tile"] in (64, 128) for o in gemms)
     assert all(1 <= o["split_k"] <= max(1, o["split_max"]) for o in gemms)
     lines = open(db).read().split("\n")
-    assert sum(ln.startswith("tnrcs-gemm") for ln in lines) == len({(o["M"], o["N"], o["K"]) for o in gemms})
+    # GEMM shapes of the plan and of the one-step plans the class tuner timed
+    assert sum(ln.startswith("tnrcs-gemm") for ln in lines) >= len({(o["M"], o["N"], o["K"]) for o in gemms})
+    # every step with more than one candidate class was timed once per key
+    steps = plan.json()["steps"]
+    tuned = [st for st in steps if st["tuned"]]
+    assert {st["key"] for st in tuned} == {st["key"] for st in steps if _candidates(st)}
+    cls_lines = [ln.split() for ln in lines if ln.startswith("tnrcs-class")]
+    assert sorted(ln[2] for ln in cls_lines) == sorted({st["key"] for st in tuned})
+    for st in tuned:
+        assert st["cls"] in _candidates(st)
     amp = torch.zeros(1 << 20, dtype=torch.complex128, device=DEV)
     plan.contract(0, plan.info()["n_slices"], amp)
     torch.cuda.synchronize()
@@ -178,6 +187,64 @@ def test_tuned_plan_vs_oracle_and_cache(tmp_path, dtype):
     assert open(db).read().split("\n") == lines
     plan.close()
     again.close()
+
+
+def _candidates(st):
+    """Kernel classes the class tuner times for a step (1 GEMM, 2 gathered,
+    3 skewed, 4 split-K): the gathered kernel against permutes + GEMM for
+    contractions of at most 2^6 terms, and every valid narrow class against
+    the others."""
+    nM, nN, nK = st["nM"], st["nN"], st["nK"]
+    if nM >= 6 and nN >= 6 and nK >= 4:
+        return [1, 2] if nK <= 6 else []
+    c = [2]
+    if nM + nN <= 6 and nK >= 4:
+        c.append(4)
+    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+        c.append(3)
+    return c if len(c) > 1 else []
+
+
+@pytest.mark.parametrize("dtype", ["c64", "f16s"])
+def test_forced_classes_vs_oracle(tmp_path, dtype):
+    """Every step with an alternative class runs in a class other than the
+    planner's rule (forced through class lines in the tuning database): the
+    plan uses them and still matches the state vector."""
+    c = make_rqc(4, 5, 12, seed=5)
+    open_q = list(range(20))
+    bits = np.zeros(20, dtype=np.uint8)
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, 24)
+    dry = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, dry_run=True)
+    forced = {}
+    for st in dry.json()["steps"]:
+        cand = _candidates(st)
+        if cand:
+            forced[st["key"]] = [k for k in cand if k != st["cls"]][0]
+    dry.close()
+    assert set(forced.values()) >= {2, 4}
+    db = str(tmp_path / "tune.txt")
+    code = {"c64": 0, "f16s": 1, "bf16s": 2}[dtype]
+    with open(db, "w") as f:
+        for key, k in forced.items():
+            f.write(f"tnrcs-class {code} {key} {k} 0.0\n")
+    print(f"forced classes {sorted(forced.values())} {dtype}", flush=True)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, tune=True, tune_db=db)
+    steps = plan.json()["steps"]
+    for st in steps:
+        if st["key"] in forced:
+            assert st["tuned"] and st["cls"] == forced[st["key"]], st
+    kinds = {o["kind"] for o in plan.json()["ops"]}
+    assert 4 in kinds and 2 in kinds
+    amp = torch.zeros(1 << 20, dtype=torch.complex128, device=DEV)
+    plan.contract(0, plan.info()["n_slices"], amp)
+    torch.cuda.synchronize()
+    err = oracle.relative_error_norm(amp.cpu().numpy(), oracle.statevector(c).reshape(-1))
+    print(f"  relative error {err:.3e}", flush=True)
+    assert err < TOL[dtype]
+    assert plan.status() & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
+    plan.close()
 
 
 def test_config5_circuits_in_one_batch_vs_oracle():

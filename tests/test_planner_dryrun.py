@@ -189,3 +189,74 @@ def test_shift_outputs_on_dry_run_plan():
     if perm:
         with pytest.raises(tnrcs.TnError):
             plan.shift_outputs(1, op=perm[0])
+
+
+def _class_candidates(st):
+    nM, nN, nK = st["nM"], st["nN"], st["nK"]
+    if nM >= 6 and nN >= 6 and nK >= 4:
+        return [1, 2] if nK <= 6 else []
+    c = [2]
+    if nM + nN <= 6 and nK >= 4:
+        c.append(4)
+    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+        c.append(3)
+    return c if len(c) > 1 else []
+
+
+def _default_class(st):
+    nM, nN, nK = st["nM"], st["nN"], st["nK"]
+    if nM >= 6 and nN >= 6 and nK >= 4:
+        return 1
+    if nM + nN <= 6 and nK >= 10:
+        return 4
+    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+        return 3
+    return 2
+
+
+@pytest.mark.parametrize("dtype", ["c64", "f16s"])
+@pytest.mark.parametrize("d,n_open,S,alt", [(8, 15, 16, 2), (12, 6, 15, 4)])
+def test_step_classes_default_rule_and_forced_classes(tmp_path, dtype, d, n_open, S, alt):
+    """Each device step's kernel class follows the planner's rule; class
+    lines in a tuning database replace it (a dry-run plan applies them
+    without timing), the forced plan still computes the amplitudes, and a
+    line naming a class that the step does not admit is ignored.  Networks
+    on 3x5 qubits where the alternative is the gathered kernel in place of
+    permutes + GEMM (alt 2) or split-K in place of the gathered kernel
+    (alt 4)."""
+    c = make_rqc(3, 5, d, 0)
+    open_q = list(range(15 - n_open, 15))
+    bits = random_bitstrings(15, 1, seed=4)[0]
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, S)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True, dtype=dtype)
+    steps = plan.json()["steps"]
+    assert len(steps) == plan.info()["n_device_steps"]
+    for st in steps:
+        assert st["cls"] == _default_class(st) and not st["tuned"]
+        a, b, cc = (list(map(int, part.split("."))) if part else [] for part in st["key"].split("/"))
+        assert a == list(range(len(a)))  # relabelled by first appearance
+        assert len(cc) == st["nM"] + st["nN"] and len(set(a) & set(b)) == st["nK"]
+    forced = {st["key"]: [k for k in _class_candidates(st) if k != st["cls"]][0]
+              for st in steps if _class_candidates(st)}
+    assert alt in forced.values()
+    fixed = [st for st in steps if st["key"] not in forced]
+    plan.close()
+    code = {"c64": 0, "f16s": 1}[dtype]
+    db = tmp_path / "tune.txt"
+    with open(db, "w") as f:
+        for key, k in forced.items():
+            f.write(f"tnrcs-class {code} {key} {k} 0.0\n")
+        for st in fixed:  # not admitted (no such class): ignored
+            f.write(f"tnrcs-class {code} {st['key']} 9 0.0\n")
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dry_run=True, dtype=dtype, tune=True, tune_db=str(db))
+    for st in plan.json()["steps"]:
+        if st["key"] in forced:
+            assert st["tuned"] and st["cls"] == forced[st["key"]]
+        else:
+            assert st["cls"] == _default_class(st)
+    amp = _run_plan(plan, plan.info()["n_slices"], n_open)
+    ref = oracle.amplitudes_sv(c, open_q, bits)
+    np.testing.assert_allclose(amp, ref, atol=1e-12)
+    plan.close()
