@@ -50,8 +50,8 @@ __device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
 // Running maximum of |re|, |im| for the range check of scaled storage; a
 // NaN counts as +inf (it comes from an overflow earlier in the same sum).
 __device__ __forceinline__ float mag_max(float m, float re, float im) {
-  if (re != re || im != im) return INFINITY;
-  return fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+  const float t = fmaxf(m, fmaxf(fabsf(re), fabsf(im)));
+  return (re != re || im != im) ? INFINITY : t;  // a select, not a branch
 }
 
 // Largest |component| over a workgroup, folded into *slot (non-negative

@@ -183,30 +183,47 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm(const E* __restrict__ A, con
   }
   float mx = 0.f;
   const int kh = lane >> 5;
+  auto result = [&](int i, int j, int r, float& re, float& im) {
+    if (FORM == TN_GEMM_3M) {
+      re = acc[0][i][j][r] - acc[1][i][j][r];
+      im = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
+    } else {
+      re = acc[0][i][j][r];
+      im = acc[1][i][j][r];
+    }
+  };
+  if (to_work) {
 #pragma unroll
-  for (int i = 0; i < WTM; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
-    for (int j = 0; j < WTN; ++j)
+      for (int j = 0; j < WTN; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int col = wn + 32 * j + c;
-        float re, im;
-        if (FORM == TN_GEMM_3M) {
-          re = acc[0][i][j][r] - acc[1][i][j][r];
-          im = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
-        } else {
-          re = acc[0][i][j][r];
-          im = acc[1][i][j][r];
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+          const int col = wn + 32 * j + c;
+          float re, im;
+          result(i, j, r, re, im);
+          reinterpret_cast<float2*>(Cout)[z * sC + (bm + row) * N + bn + col] = make_float2(re, im);
+          if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
-        const int64_t o = (bm + row) * N + bn + col;
-        if (to_work) {
-          reinterpret_cast<float2*>(Cout)[z * sC + o] = make_float2(re, im);
-        } else {
+  } else {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+          const int col = wn + 32 * j + c;
+          float re, im;
+          result(i, j, r, re, im);
           mx = mag_max(mx, re, im);
-          reinterpret_cast<E*>(Cout)[z * sC + o] = from_f2<E>(re * out_scale, im * out_scale);
+          reinterpret_cast<E*>(Cout)[z * sC + (bm + row) * N + bn + col] = from_f2<E>(re * out_scale, im * out_scale);
+          // keep the accumulator reads of one 32x32 block together (hoisting
+          // them all at once exhausts the registers of the widest tiles)
+          if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
-      }
+  }
   // the block reduction reuses the (now idle) stage buffers: no LDS beyond
   // the two stages, so two workgroups fit in one CU's LDS
   if (!to_work) record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
