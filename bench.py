@@ -89,12 +89,17 @@ def cpu_baseline(w, sub_log2: int):
             "seconds": dt}
 
 
-def run_network(tnrcs, torch, w, dtype, form, K, W, graph=True, profile=True):
+def run_network(tnrcs, torch, w, dtype, form, K, W, graph=True, profile=True, tune=True, tune_db=None):
+    """Plans (with the autotuner unless tune is False: kernel class per step,
+    GEMM tile / split / variant per shape; plan-time work, outside the timed
+    region), warms up W slices, then times K slices on the GPU."""
     t0 = time.perf_counter()
     plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, gemm_form=form, use_graph=graph,
-                      dtype=dtype)
+                      dtype=dtype, tune=tune, tune_db=tune_db)
+    t_plan = time.perf_counter() - t0
     info = plan.info()
-    log(f"[bench] {dtype}: planned in {time.perf_counter() - t0:.2f} s: {info['n_device_steps']} device steps, "
+    log(f"[bench] {dtype}: planned{' and tuned' if tune else ''} in {t_plan:.2f} s: "
+        f"{info['n_device_steps']} device steps, "
         f"{info['n_kernels']} kernels/slice, arena {info['arena_bytes'] / 2**30:.1f} GiB, "
         f"{info['flops_per_slice']:.3e} flop/slice")
     stream = torch.cuda.current_stream()
@@ -114,7 +119,7 @@ def run_network(tnrcs, torch, w, dtype, form, K, W, graph=True, profile=True):
     gpu_s = ev0.elapsed_time(ev1) / 1e3
     flags = plan.status()
     res = {"plan": plan, "info": info, "sec_per_slice": gpu_s / K, "tflops": info["flops_per_slice"] * K / gpu_s / 1e12,
-           "flags": flags, "amp": amp.cpu().numpy()}
+           "flags": flags, "amp": amp.cpu().numpy(), "plan_s": t_plan}
     log(f"[bench] {dtype}: {K} slices in {gpu_s:.3f} s: {gpu_s / K:.4f} s/slice, {res['tflops']:.2f} complex "
         f"TFLOP/s, flags={flags}")
     if profile:
@@ -451,6 +456,9 @@ def main():
     ap.add_argument("--form", default="auto", choices=["auto", "4m", "3m"])
     ap.add_argument("--dtype", default="c64", choices=["c64", "f16s", "bf16s"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="plan with the default rules instead of the autotuner")
+    ap.add_argument("--tune-db", default=None,
+                    help="tuning database file (choices found there are reused, new ones appended)")
     ap.add_argument("--no-extra", action="store_true", help="skip the precision variants and microbenchmarks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sub-log2", type=int, default=28)
@@ -481,7 +489,8 @@ def main():
     log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
     n_slices = 1 << len(w.sliced)
     K, W = min(args.steps, n_slices - args.warmup), args.warmup
-    main_res = run_network(tnrcs, torch, w, args.dtype, args.form, K, W, graph=not args.no_graph)
+    main_res = run_network(tnrcs, torch, w, args.dtype, args.form, K, W, graph=not args.no_graph,
+                           tune=not args.no_tune, tune_db=args.tune_db)
     by_kind, split = kernel_split(main_res, args.dtype)
     roof = roofline(by_kind, args.dtype)
     info = main_res["info"]
@@ -504,7 +513,8 @@ def main():
         for dt in ("f16s", "bf16s"):
             if dt == args.dtype:
                 continue
-            r = run_network(tnrcs, torch, w, dt, "auto", K, W, profile=(dt == "f16s"))
+            r = run_network(tnrcs, torch, w, dt, "auto", K, W, profile=(dt == "f16s"), tune=not args.no_tune,
+                            tune_db=args.tune_db)
             err = float(np.linalg.norm(r["amp"] - main_res["amp"]) / np.linalg.norm(main_res["amp"]))
             prec[dt] = {"sec_per_slice": r["sec_per_slice"], "complex_tflops": r["tflops"],
                         "time_ratio_vs_" + args.dtype: main_res["sec_per_slice"] / r["sec_per_slice"],
@@ -554,6 +564,8 @@ def main():
             "bytes_per_slice": info["bytes_per_slice"],
             "gemm_form": args.form,
             "graph": not args.no_graph,
+            "tuned": not args.no_tune,
+            "plan_s": main_res["plan_s"],
             "kernels_per_slice": info["n_kernels"],
             "kernel_split": split,
             "slice_roofline_frac": slice_roofline_frac(main_res, args.dtype),

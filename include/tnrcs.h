@@ -142,11 +142,12 @@ typedef struct {
  * kernel when the contraction has at most 2^6 terms; gathered, skewed and
  * split-K against each other for steps with too few outputs for the GEMM)
  * is run in each on a one-step plan of the same operand layouts over
- * zero-filled scratch buffers (at most a third of the free device memory;
+ * scratch buffers of random values (at most a third of the free device memory;
  * larger steps keep the default rule), and the fastest is planned.  Tile:
  * for each distinct dense-GEMM shape of the plan (dtype, M, N, K, form)
- * every valid tile size and K-split count is timed with HIP events on the
- * plan's own buffers (the arena is zero-filled first) and the fastest kept.
+ * every valid tile size, K-split count and kernel variant is timed with HIP
+ * events on the plan's own buffers (the arena is filled with random values
+ * first: the matrix cores run faster on zeros) and the fastest kept.
  * Results are cached per process and, with tune_db, in a file (lines
  * "tnrcs-class dtype key class ms" and "tnrcs-gemm dtype M N K form cap tile
  * split occ ms"; the key is the step's operand and result layouts with the

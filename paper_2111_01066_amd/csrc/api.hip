@@ -318,14 +318,16 @@ static int calibrate(tn_plan_s* p, int64_t slice = 0) {
   return upload_scales(p);
 }
 
-// Autotuning: zero the arena, then time each dense GEMM step's variants on
-// its own buffers (shapes seen before are answered from the cache).
+// Autotuning: fill the arena with random values of the storage format, then
+// time each dense GEMM step's variants on its own buffers (shapes seen before
+// are answered from the cache).
 static int tune_plan(tn_plan_s* p) {
   PlanCore& P = p->core;
   bool any = false;
   for (const Op& op : P.ops) any |= op.kind == kOpGemm;
   if (!any) return TN_OK;
-  if (P.arena_elems > 0) HIP_TRY(hipMemset(p->d_arena, 0, (size_t)P.arena_elems * p->eb), "clear arena");
+  if (P.arena_elems > 0)
+    HIP_TRY(launch_fill_random(p->d_arena, P.arena_elems * p->eb, P.opts.dtype, nullptr), "fill arena");
   HIP_TRY(hipDeviceSynchronize(), "tuner synchronize");
   for (Op& op : P.ops) {
     if (op.kind != kOpGemm) continue;
@@ -342,8 +344,8 @@ static int tune_plan(tn_plan_s* p) {
 
 // Kernel-class autotuning (the permute/GEMM fusion choice).  A step whose
 // shape admits more than one kernel class is run in each candidate class on
-// a one-step plan with the same operand layouts over zero-filled buffers of
-// its own; the fastest class overrides the planner's rule.  Candidates: the
+// a one-step plan with the same operand layouts over buffers of its own
+// filled with random values; the fastest class overrides the planner's rule.  Candidates: the
 // gathered kernel against permutes + GEMM when the contraction is short
 // (2^nK <= 2^kFuseMaxK terms), and gathered, split-K and skewed against each
 // other for steps too narrow for the GEMM.  Steps whose buffers would exceed
@@ -392,7 +394,7 @@ static int time_class(const PlanCore& P, const std::vector<int>& a, const std::v
   const std::pair<char**, int64_t> bufs[] = {{&A, na}, {&B, nb}, {&C, nc}, {&q.d_arena, Q.arena_elems}};
   for (const auto& [ptr, n] : bufs)
     if (e == hipSuccess && (e = hipMalloc((void**)ptr, (size_t)std::max<int64_t>(n * q.eb, 256))) == hipSuccess)
-      e = hipMemset(*ptr, 0, (size_t)std::max<int64_t>(n * q.eb, 256));
+      e = launch_fill_random(*ptr, std::max<int64_t>(n * q.eb, 256), Q.opts.dtype, nullptr);
   if (e == hipSuccess) e = hipMalloc((void**)&q.d_maxslots, (size_t)std::max(Q.n_slots, 1) * 4);
   if (e == hipSuccess) e = hipMemset(q.d_maxslots, 0, (size_t)std::max(Q.n_slots, 1) * 4);
   if (e == hipSuccess) e = hipEventCreate(&e0);

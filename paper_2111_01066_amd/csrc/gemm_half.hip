@@ -229,6 +229,148 @@ __global__ __launch_bounds__(256, OCC) void k_hgemm(const E* __restrict__ A, con
   if (!to_work) record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
 }
 
+// Ping-pong schedule (4M form): eight waves, two per SIMD, in two groups of
+// four.  In each K stage one group runs its MFMAs on the stage in LDS while
+// the other stores its share of the next stage (loaded into registers one
+// stage earlier) into the other LDS buffer and issues the global loads of
+// the stage after; a barrier hands the roles over, and a second one ends the
+// stage.  The MFMA pipe of a SIMD is fed by one wave at a time, without the
+// stage stores and barriers of a single-wave loop between its MFMAs.
+// 256x128 workgroup tile, 64x64 per wave; needs M % 256 == N % 128 ==
+// k_len % 32 == 0.
+template <typename H, typename E>
+__global__ __launch_bounds__(512, 1) void k_hgemm_pp(const E* __restrict__ A, const E* __restrict__ B,
+                                                   void* __restrict__ Cout, int64_t N, int64_t K, int64_t k_len,
+                                                   int64_t sA, int64_t sB, int64_t sC, float out_scale,
+                                                   float* maxslot, int to_work, int64_t Mt, int64_t Nt) {
+  typedef typename Frag<H>::T F;
+  constexpr int BK = 32, BM = 256, BN = 128, LDK = BK + 8, P = 2;
+  __shared__ __attribute__((aligned(16))) H As[2][P][BM][LDK];
+  __shared__ __attribute__((aligned(16))) H Bs[2][P][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2;  // group 0 computes first in every stage
+  const int gt = tid & 255;   // thread index within the group
+  int64_t tm, tn, z;
+  xcd_tile(blockIdx.x, Mt, Nt, gridDim.x, tm, tn, z);
+  const int64_t bm = tm * BM, bn = tn * BN;
+  A += z * sA;
+  B += z * sB;
+  const int wm = (wave & 3) * 64, wn = grp * 64;
+  floatx16 acc[2][2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = floatx16{};
+  // this thread's share of every stage: 16 complex of A row grp*128 + gt/2
+  // and 8 complex of B row grp*64 + gt/4
+  const int arow = grp * 128 + (gt >> 1), ak = (gt & 1) * 16;
+  const int brow = grp * 64 + (gt >> 2), bk = (gt & 3) * 8;
+  const uint4* Ap = reinterpret_cast<const uint4*>(A + (bm + arow) * K + ak);
+  const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + brow) * K + bk);
+  uint4 ra[4], rb[2];
+  const int64_t nst = k_len / BK;
+  auto load = [&](int64_t st) {
+    const int64_t o = st * (BK / 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ra[j] = Ap[o + j];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) rb[j] = Bp[o + j];
+  };
+  auto store = [&](int buf) {
+    store_stage<P, BM, LDK, 4, H>(As[buf], ra, arow, ak);
+    store_stage<P, BN, LDK, 2, H>(Bs[buf], rb, brow, bk);
+  };
+  const int c = lane & 31, kq = (lane >> 5) * 8;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      F a[P][2], b[P][2];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[p][i] = *reinterpret_cast<const F*>(&As[buf][p][wm + 32 * i + c][kk + kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[p][j] = *reinterpret_cast<const F*>(&Bs[buf][p][wn + 32 * j + c][kk + kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+          acc[1][i][j] = Frag<H>::mfma(a[0][i], b[1][j], acc[1][i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        uint4 t = __builtin_bit_cast(uint4, a[1][i]);
+        t.x ^= 0x80008000u;
+        t.y ^= 0x80008000u;
+        t.z ^= 0x80008000u;
+        t.w ^= 0x80008000u;
+        const F na = __builtin_bit_cast(F, t);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[0][i][j] = Frag<H>::mfma(na, b[1][j], acc[0][i][j]);
+          acc[1][i][j] = Frag<H>::mfma(a[1][i], b[0][j], acc[1][i][j]);
+        }
+      }
+    }
+  };
+  load(0);
+  store(0);
+  load(nst > 1 ? 1 : 0);
+  __syncthreads();
+  // one loop per group (the same barriers in the same order), so that the
+  // registers a group's loads land in stay put across its MFMAs.  nx: the
+  // stage after next, clamped: past the end the last stage is re-read and
+  // its copy goes to the buffer nobody reads any more.
+  // (the compiler may still move MFMAs, which touch registers only, across
+  // a barrier into the neighbouring phase; fencing them in measured slower)
+  auto handover = [&]() { __syncthreads(); };
+  if (grp == 0) {
+    for (int64_t st = 0; st < nst; ++st) {
+      const int cur = (int)(st & 1);
+      compute(cur);
+      handover();
+      store(cur ^ 1);
+      load(st + 2 < nst ? st + 2 : nst - 1);
+      handover();
+    }
+  } else {
+    for (int64_t st = 0; st < nst; ++st) {
+      const int cur = (int)(st & 1);
+      store(cur ^ 1);
+      load(st + 2 < nst ? st + 2 : nst - 1);
+      handover();
+      compute(cur);
+      handover();
+    }
+  }
+  float mx = 0.f;
+  const int kh = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int col = wn + 32 * j + c;
+        const float re = acc[0][i][j][r], im = acc[1][i][j][r];
+        const int64_t o = z * sC + (bm + row) * N + bn + col;
+        if (to_work) {
+          reinterpret_cast<float2*>(Cout)[o] = make_float2(re, im);
+        } else {
+          mx = mag_max(mx, re, im);
+          reinterpret_cast<E*>(Cout)[o] = from_f2<E>(re * out_scale, im * out_scale);
+        }
+        if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+  if (!to_work) record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
+}
+
 // C[i] = (sum over slabs s, in order, of W[s][i]) * scale, rounded to E.
 template <typename E>
 __global__ __launch_bounds__(256) void k_hsplit_sum(const float2* __restrict__ W, E* __restrict__ C, int64_t n,
@@ -269,9 +411,17 @@ static void hgemm_dispatch(int64_t M, int64_t z, hipStream_t s, const E* A, cons
                          scale, maxslot, to_work, Mt, Nt);
     return;
   }
+  if constexpr (FORM == TN_GEMM_4M) {
+    if (occ == 3 && M % 256 == 0 && kl % 32 == 0) {
+      const int64_t Mt = M / 256, Nt = N / 128;
+      hipLaunchKernelGGL((k_hgemm_pp<H, E>), dim3((unsigned)(Mt * Nt * z)), dim3(512), 0, s, A, B, C, N, K, kl, sA,
+                         sB, sC, scale, maxslot, to_work, Mt, Nt);
+      return;
+    }
+  }
   // two waves per SIMD (registers capped at 256) hide latency on short K;
   // one wave per SIMD (no cap) pipelines long K better
-  if (occ == 0) occ = kl >= 16384 ? 1 : 2;
+  if (occ == 0 || occ == 3) occ = kl >= 16384 ? 1 : 2;
   const int64_t Mt = M / 128, Nt = N / 128;
   const dim3 grid((unsigned)(Mt * Nt * z));
   if (kl % 32 == 0) {

@@ -21,6 +21,8 @@ inline int elem_bytes_of(int dtype) { return dtype == TN_DTYPE_C64 ? 8 : 4; }
 hipError_t launch_set_ctrl(Ctrl* ctrl, int64_t cursor, void* amp, hipStream_t s, bool clear_flags = false);
 // dst += src over n complex128 entries.
 hipError_t launch_add_amp(const double* src, double* dst, int64_t n, hipStream_t s);
+// bytes / 4 words of pseudo-random values of the storage format (tuning data)
+hipError_t launch_fill_random(void* p, int64_t bytes, int dtype, hipStream_t s);
 // Copies every sliced leaf's sub-block of the current slice; with kappa
 // (scaled storage) also stores the product of their rounding factors in ctrl.
 hipError_t launch_bind(int elem_bytes, const void* leaves, void* bound, const BindDesc* descs, int n_desc,
@@ -33,7 +35,8 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
                            int64_t batch, int form, hipStream_t s, float2* work = nullptr, int splits = 1,
                            int tile = 0);
 // scaled FP16/BF16 GEMM on half MFMA; C = A B^T * out_scale; max |A B^T| recorded in *maxslot.
-// tile: 0 auto, 64 or 128; occ (128 tiles): 0 auto, 1 or 2 waves per SIMD.
+// tile: 0 auto, 64 or 128; occ (128 tiles): 0 auto, 1 or 2 waves per SIMD, 3 the
+// ping-pong 256x128 kernel (4M, M % 256 == 0, K per split % 32 == 0).
 hipError_t launch_gemm_half(int dtype, const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                             int64_t batch, int form, hipStream_t s, float2* work, int splits, float out_scale,
                             float* maxslot, int tile = 0, int occ = 0);

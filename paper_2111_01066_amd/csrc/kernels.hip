@@ -47,6 +47,38 @@ hipError_t launch_add_amp(const double* src, double* dst, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
+// Fills n 32-bit words with hashed pseudo-random values of the storage
+// format (FP32 in [-1, 1) for complex64; two FP16 / BF16 halves of random
+// sign with magnitudes in [0.5, 1) otherwise): tuning data with the power
+// draw of real operands (the matrix cores run measurably faster on zeros).
+__global__ __launch_bounds__(256) void k_fill_random(uint32_t* __restrict__ p, int64_t n, int kind) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 2654435761u + (uint32_t)(i >> 32);
+    h ^= h >> 15;
+    h *= 0x2c1b3c6du;
+    h ^= h >> 12;
+    h *= 0x297a2d39u;
+    h ^= h >> 15;
+    uint32_t w;
+    if (kind == TN_DTYPE_C64) {
+      w = __float_as_uint((float)(int32_t)h * 0x1p-31f);
+    } else if (kind == TN_DTYPE_F16S) {
+      w = ((h & 0x83FFu) | 0x3800u) | ((((h >> 16) & 0x83FFu) | 0x3800u) << 16);
+    } else {
+      w = ((h & 0x807Fu) | 0x3F00u) | ((((h >> 16) & 0x807Fu) | 0x3F00u) << 16);
+    }
+    p[i] = w;
+  }
+}
+
+hipError_t launch_fill_random(void* p, int64_t bytes, int dtype, hipStream_t s) {
+  const int64_t n = bytes / 4;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 16384)), dim3(256), 0, s,
+                     (uint32_t*)p, n, dtype);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------- bind --
 // Copies, for every sliced leaf, the sub-tensor selected by the current slice
 // id (its sliced wires are the leaf's top bits) into the bound-leaf region.

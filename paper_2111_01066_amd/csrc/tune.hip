@@ -3,7 +3,8 @@
 // fastest.  Results are cached per process by (dtype, M, N, K, form, split
 // capacity) and, when a database path is given, in a plain text file
 // ("tnrcs-gemm dtype M N K form cap tile split occ ms" per line; occ is the
-// waves-per-SIMD variant of the FP16/BF16 128x128 kernel, 0 elsewhere).
+// variant of the FP16/BF16 128-row kernels: 1 or 2 waves per SIMD of the
+// 128x128 kernel, 3 the ping-pong 256x128 kernel; 0 elsewhere).
 // The same file holds the kernel-class choices of whole steps
 // ("tnrcs-class dtype key class ms"), which the plan builder times itself.
 #include <hip/hip_runtime.h>
@@ -104,6 +105,8 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
       if (dtype != TN_DTYPE_C64 && tile == 128) {
         variants.push_back({tile, sp, 1});
         variants.push_back({tile, sp, 2});
+        // the ping-pong 256x128 kernel (4M form only)
+        if (g.form == TN_GEMM_4M && g.M % 256 == 0 && (g.K / sp) % 32 == 0) variants.push_back({tile, sp, 3});
       } else {
         variants.push_back({tile, sp, 0});
       }

@@ -247,6 +247,41 @@ def test_forced_classes_vs_oracle(tmp_path, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s"])
+def test_forced_pingpong_gemm_vs_oracle(tmp_path, dtype):
+    """The ping-pong 256x128 FP16/BF16 GEMM variant (tuning choice occ 3),
+    forced through a GEMM line in the tuning database for every eligible
+    step of a sliced 20-qubit network: the plan uses it and matches the
+    state vector."""
+    c = make_rqc(4, 5, 12, seed=5)
+    open_q = list(range(20))
+    bits = np.zeros(20, dtype=np.uint8)
+    ns = network_structure(c, open_q)
+    pairs = bisection_order(ns, seed=0)
+    sliced = slice_to_fit(ns, pairs, 24)
+    dry = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, dry_run=True, tune=True)
+    code = {"f16s": 1, "bf16s": 2}[dtype]
+    lines = [f"tnrcs-gemm {code} {o['M']} {o['N']} {o['K']} {o['form']} {o['split_max']} 128 1 3 0.0"
+             for o in dry.json()["ops"]
+             if o["kind"] == 1 and o["form"] == 1 and o["M"] % 256 == 0 and o["N"] % 128 == 0 and o["K"] % 32 == 0]
+    dry.close()
+    assert lines
+    db = str(tmp_path / "tune.txt")
+    with open(db, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"ping-pong GEMM forced on {len(lines)} shape(s), {dtype}", flush=True)
+    plan = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, tune=True, tune_db=db)
+    assert sum(o["kind"] == 1 and o["occ"] == 3 for o in plan.json()["ops"]) >= len(lines)
+    amp = torch.zeros(1 << 20, dtype=torch.complex128, device=DEV)
+    plan.contract(0, plan.info()["n_slices"], amp)
+    torch.cuda.synchronize()
+    err = oracle.relative_error_norm(amp.cpu().numpy(), oracle.statevector(c).reshape(-1))
+    print(f"  relative error {err:.3e}", flush=True)
+    assert err < TOL[dtype]
+    assert plan.status() & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
+    plan.close()
+
+
 def test_config5_circuits_in_one_batch_vs_oracle():
     """Four of the 512 frozen config-5 circuits, scaled FP16 in one batch,
     against the oracle's pairwise FP64 contraction of the same order: 5
