@@ -49,7 +49,7 @@ extern "C" {
 #define TN_E_TOPOLOGY (-2)    /* order is not a full tree / unknown wire */
 #define TN_E_MEM (-3)         /* arena exceeds the budget or device memory */
 #define TN_E_HIP (-4)         /* a HIP runtime call failed */
-#define TN_E_UNSUPPORTED (-5) /* valid request this build does not handle */
+#define TN_E_UNSUPPORTED (-5) /* valid request this library does not handle */
 #define TN_E_NUMERIC (-6)     /* non-finite or out-of-range values seen */
 
 #define TN_DTYPE_C64 0   /* complex64 storage, FP32 arithmetic */

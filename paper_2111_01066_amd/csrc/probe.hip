@@ -1,4 +1,4 @@
-// Measurement probes of the machine ceilings that the kernels are judged
+// Measurement probes of the machine ceilings that the kernels are compared
 // against: an MFMA issue loop per data type (no memory traffic) and a
 // streaming device copy with 16-byte accesses.
 #include <hip/hip_runtime.h>
