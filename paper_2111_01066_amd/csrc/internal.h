@@ -14,7 +14,7 @@ namespace tnrcs {
 
 constexpr int kMaxRank = 48;  // bits of a device tensor index
 constexpr int kMaxRuns = 48;  // runs of a bit-deposit map
-constexpr int kSkinnyMaxLog2 = 12;  // the skewed kernel keeps 2^(nK+nN) <= 2^12 B entries in LDS
+constexpr int kSkinnyMaxLog2 = 11;  // the skewed kernel keeps 2^(nK+nN) <= 2^11 B entries in LDS
 
 // Bit-deposit map: value bit (src + i) goes to target bit (dst + i) for
 // i < len, for each run.  Built from "value bit j -> target position pos[j]".

@@ -383,82 +383,166 @@ hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, cons
 // ----------------------------------------------------------------- skinny --
 // Skewed contraction (M large, N and K small; Supplement, CPU-architecture
 // section: the small operand stays in fast local memory and the large one is
-// read once): B (2^(nK+nN) <= 4096 entries) and A's K offsets are staged in
-// LDS; each thread owns one m, streams its A row once (consecutive threads
-// take consecutive m, so A is read coalesced wherever A's low bits are M
-// bits) and keeps its 2^nN outputs in registers; C row m is written once as
-// one contiguous run of 2^nN entries.
+// read once): B (2^(nK+nN) <= 2048 entries) and A's K offsets are kept in
+// LDS; each thread owns whole rows m (2^nN outputs in registers), A is read
+// once and C written once, both through coalesced accesses where the layout
+// allows.
 
-template <int NN, typename E>
+typedef unsigned int row_u32x4 __attribute__((ext_vector_type(4)));
+
+// Each pass of a workgroup covers 256 R consecutive m (R per thread, at
+// stride 256), whose C rows form one contiguous run of 256 R NN entries: the
+// outputs are staged in LDS and written back in coalesced 16-byte
+// nontemporal stores.  NK > 0: A's layout is [M bits, K bits] in order
+// (nK = log2(NK)), so the pass's A rows are one contiguous run as well,
+// loaded the same way; NK == 0: any layout, each thread gathers its rows
+// through the offset table (consecutive m are adjacent in A wherever A's
+// low bits are M bits).  R > 1 keeps more loads in flight per thread.
+template <int NN, int NK, int R, typename E>
 __global__ __launch_bounds__(256) void k_skinny(const E* __restrict__ A, const E* __restrict__ B, E* __restrict__ C,
                                                const IndexOp op, float* maxslot) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int nk = 1 << op.nK;
-  float2* Bs = reinterpret_cast<float2*>(smem);                                  // [nk][NN]
-  uint64_t* kofs = reinterpret_cast<uint64_t*>(smem + (size_t)nk * NN * sizeof(float2));  // [nk]
+  constexpr int PM = 256 * R;  // rows per pass
+  const int nk = NK > 0 ? NK : 1 << op.nK;
+  E* sC = reinterpret_cast<E*>(smem);                          // [PM][NN]
+  E* sA = sC + PM * NN;                                        // [PM][NK] (NK > 0)
+  float2* Bs = reinterpret_cast<float2*>(sA + PM * NK);        // [nk][NN]
+  uint64_t* kofs = reinterpret_cast<uint64_t*>(Bs + nk * NN);  // [nk] (NK == 0)
   for (int i = threadIdx.x; i < nk * NN; i += blockDim.x) {
     const int k = i / NN, n = i % NN;
     Bs[i] = to_f2(B[dep((uint64_t)n, op.bN) | dep((uint64_t)k, op.bK)]);
   }
-  for (int k = threadIdx.x; k < nk; k += blockDim.x) kofs[k] = dep((uint64_t)k, op.aK);
+  if (NK == 0)
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) kofs[k] = dep((uint64_t)k, op.aK);
   __syncthreads();
-  const int64_t nm = (int64_t)1 << op.nM;
+  const int tid = threadIdx.x;
+  const int64_t nm = (int64_t)1 << op.nM;  // a multiple of PM
   float mx = 0.f;
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t am = dep((uint64_t)m, op.aM);
-    float re[NN], im[NN];
+  for (int64_t m0 = (int64_t)blockIdx.x * PM; m0 < nm; m0 += (int64_t)gridDim.x * PM) {
+    float re[R][NN], im[R][NN];
 #pragma unroll
-    for (int n = 0; n < NN; ++n) re[n] = im[n] = 0.f;
-    for (int k = 0; k < nk; ++k) {
-      const float2 x = to_f2(A[am | kofs[k]]);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int n = 0; n < NN; ++n) re[r][n] = im[r][n] = 0.f;
+    auto madd = [&](int r, const float2 x, int k) {
       const float2* b = Bs + k * NN;
 #pragma unroll
       for (int n = 0; n < NN; ++n) {
         const float2 y = b[n];
-        re[n] = fmaf(x.x, y.x, re[n]);
-        re[n] = fmaf(-x.y, y.y, re[n]);
-        im[n] = fmaf(x.x, y.y, im[n]);
-        im[n] = fmaf(x.y, y.x, im[n]);
+        re[r][n] = fmaf(x.x, y.x, re[r][n]);
+        re[r][n] = fmaf(-x.y, y.y, re[r][n]);
+        im[r][n] = fmaf(x.x, y.y, im[r][n]);
+        im[r][n] = fmaf(x.y, y.x, im[r][n]);
+      }
+    };
+    if constexpr (NK > 0) {
+      constexpr int CH = PM * NK * (int)sizeof(E) / 16;  // 16-byte chunks of the pass's A rows
+      const row_u32x4* src = reinterpret_cast<const row_u32x4*>(A + (m0 << op.nK));
+      row_u32x4 v[(CH + 255) / 256];
+#pragma unroll
+      for (int i = 0; i < (CH + 255) / 256; ++i) {
+        const int c = i * 256 + tid;
+        if (CH % 256 == 0 || c < CH) v[i] = src[c];
+      }
+#pragma unroll
+      for (int i = 0; i < (CH + 255) / 256; ++i) {
+        const int c = i * 256 + tid;
+        if (CH % 256 == 0 || c < CH) reinterpret_cast<row_u32x4*>(sA)[c] = v[i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) madd(r, to_f2(sA[(r * 256 + tid) * NK + k]), k);
+    } else {
+      uint64_t am[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) am[r] = dep((uint64_t)(m0 + r * 256 + tid), op.aM);
+      for (int k = 0; k < nk; ++k) {
+        float2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = to_f2(A[am[r] | kofs[k]]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) madd(r, x[r], k);
       }
     }
-    E* c = C + m * NN;
 #pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      mx = mag_max(mx, re[n], im[n]);
-      c[n] = from_f2<E>(re[n] * op.out_scale, im[n] * op.out_scale);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        mx = mag_max(mx, re[r][n], im[r][n]);
+        sC[(r * 256 + tid) * NN + n] = from_f2<E>(re[r][n] * op.out_scale, im[r][n] * op.out_scale);
+      }
+    __syncthreads();
+    constexpr int CC = PM * NN * (int)sizeof(E) / 16;  // 16-byte chunks of the pass's C rows
+    row_u32x4* dst = reinterpret_cast<row_u32x4*>(C + m0 * NN);
+#pragma unroll
+    for (int i = 0; i < (CC + 255) / 256; ++i) {
+      const int c = i * 256 + tid;
+      if (CC % 256 == 0 || c < CC) __builtin_nontemporal_store(reinterpret_cast<const row_u32x4*>(sC)[c], dst + c);
     }
+    __syncthreads();
   }
-  record_max(maxslot, mx);
+  record_max_in(maxslot, mx, reinterpret_cast<float*>(smem));
 }
 
-size_t skinny_lds_bytes(const IndexOp& op) {
+// LDS of one workgroup: staged C rows, staged A rows (a_rows: A's layout is
+// [M bits, K bits]), B as FP32 pairs and A's K offsets; pm rows per pass.
+size_t skinny_lds_bytes(const IndexOp& op, int elem_bytes, bool a_rows, int pm) {
   const size_t nk = (size_t)1 << op.nK, nn = (size_t)1 << op.nN;
-  return nk * nn * sizeof(float2) + nk * sizeof(uint64_t);
+  return pm * nn * elem_bytes + (a_rows ? pm * nk * elem_bytes : 0) + nk * nn * sizeof(float2) +
+         (a_rows ? 0 : nk * sizeof(uint64_t));
+}
+
+// Rows per thread and pass: the most of 4, 2, 1 whose staged rows fit in
+// 32 KB, so that with B and the offset table (at most 32 KB) a workgroup
+// stays within 64 KB of LDS.  A tensor with fewer rows than one such pass
+// uses 1.
+template <int NN, int NK, typename E>
+constexpr int skinny_rows() {
+  constexpr int row = (NN + NK) * (int)sizeof(E);
+  return 1024 * row <= 32768 ? 4 : (512 * row <= 32768 ? 2 : 1);
+}
+
+template <int NN, int NK, typename E>
+static void launch_skinny_k(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  constexpr int RX = skinny_rows<NN, NK, E>();
+  const int64_t nm = (int64_t)1 << op.nM;
+  const bool wide = RX > 1 && nm >= 256 * RX;
+  const int pm = wide ? 256 * RX : 256;
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>(nm / pm, 8192)));
+  const size_t lds = skinny_lds_bytes(op, (int)sizeof(E), NK > 0, pm);
+  if (wide)
+    hipLaunchKernelGGL((k_skinny<NN, NK, RX, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+  else
+    hipLaunchKernelGGL((k_skinny<NN, NK, 1, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
+}
+
+template <int NN, typename E>
+static void launch_skinny_nn(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  // A's layout is [M bits, K bits], both in order: contiguous rows
+  const bool rows = op.aK.n == 1 && op.aK.src[0] == 0 && op.aK.dst[0] == 0 && op.aK.len[0] == op.nK &&
+                    op.aM.n == 1 && op.aM.src[0] == 0 && op.aM.dst[0] == op.nK && op.aM.len[0] == op.nM;
+  if (rows && op.nK == 1)
+    launch_skinny_k<NN, 2>(A, B, C, op, maxslot, s);
+  else if (rows && op.nK == 2)
+    launch_skinny_k<NN, 4>(A, B, C, op, maxslot, s);
+  else if (rows && op.nK == 3)
+    launch_skinny_k<NN, 8>(A, B, C, op, maxslot, s);
+  else
+    launch_skinny_k<NN, 0>(A, B, C, op, maxslot, s);
 }
 
 template <typename E>
 static hipError_t launch_skinny_t(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
-  const int64_t nm = (int64_t)1 << op.nM;
-  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((nm + 255) / 256, 8192)));
-  const size_t lds = skinny_lds_bytes(op);
+  if (op.nM < 8) return hipErrorInvalidValue;  // whole 256-row passes
   switch (op.nN) {
-    case 0:
-      hipLaunchKernelGGL((k_skinny<1, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_skinny<2, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_skinny<4, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_skinny<8, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_skinny<16, E>), g, dim3(256), lds, s, A, B, C, op, maxslot);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 0: launch_skinny_nn<1>(A, B, C, op, maxslot, s); break;
+    case 1: launch_skinny_nn<2>(A, B, C, op, maxslot, s); break;
+    case 2: launch_skinny_nn<4>(A, B, C, op, maxslot, s); break;
+    case 3: launch_skinny_nn<8>(A, B, C, op, maxslot, s); break;
+    case 4: launch_skinny_nn<16>(A, B, C, op, maxslot, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

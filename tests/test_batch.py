@@ -200,7 +200,7 @@ def _candidates(st):
     c = [2]
     if nM + nN <= 6 and nK >= 4:
         c.append(4)
-    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+    if nN <= 4 and nK + nN <= 11 and nM >= 8:
         c.append(3)
     return c if len(c) > 1 else []
 

@@ -28,7 +28,18 @@ CASES = [
     (list(range(60, 70)) + [0, 1, 2], list(range(70, 79)) + [0, 1, 2], list(range(60, 70)) + list(range(70, 79))),
     # dense with 64-wide free extents (the 64x64 GEMM tile, FP16 included)
     (list(range(80, 88)) + list(range(6)), list(range(90, 96)) + list(range(6)), list(range(80, 88)) + list(range(90, 96))),
+] + [
+    # skewed: A as [M bits, K bits] (contiguous rows; 1, 2 or 4 rows per thread and pass),
+    # K bits elsewhere (gathered rows), no K at all, and the largest B (2^11 entries)
+    (list(range(12)) + [100], [101, 100], list(range(12)) + [101]),
+    (list(range(9)) + [100, 102, 104], [101, 100, 103, 102, 105, 104, 106], list(range(9)) + [101, 103, 105, 106]),
+    (list(range(10)) + [100, 102], [102, 101, 100, 103, 104], list(range(10)) + [101, 103, 104]),
+    (list(range(6)) + [200] + list(range(6, 11)) + [201], [201, 202, 200, 203], list(range(11)) + [202, 203]),
+    (list(range(8)), [300, 301], list(range(8)) + [300, 301]),
+    (list(range(8)) + list(range(400, 407)), list(range(400, 407)) + [410, 411, 412, 413],
+     list(range(8)) + [410, 411, 412, 413]),
 ]
+SKEWED = CASES[-6:]
 
 
 def _rand(rng, r):
@@ -53,6 +64,13 @@ def test_pair_dryrun(la, lb, lc):
     it.ext = {3: A, 4: B, 5: C}
     it.run_ops()
     np.testing.assert_allclose(C, _ref(A, la, B, lb, lc), atol=1e-12)
+    pp.close()
+
+
+@pytest.mark.parametrize("la,lb,lc", SKEWED)
+def test_pair_skewed_cases_plan_the_skewed_kernel(la, lb, lc):
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+    assert [o["kind"] for o in pp.json()["ops"]] == [3]
     pp.close()
 
 

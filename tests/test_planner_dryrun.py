@@ -198,7 +198,7 @@ def _class_candidates(st):
     c = [2]
     if nM + nN <= 6 and nK >= 4:
         c.append(4)
-    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+    if nN <= 4 and nK + nN <= 11 and nM >= 8:
         c.append(3)
     return c if len(c) > 1 else []
 
@@ -209,7 +209,7 @@ def _default_class(st):
         return 1
     if nM + nN <= 6 and nK >= 10:
         return 4
-    if nN <= 4 and nK + nN <= 12 and nM >= 8:
+    if nN <= 4 and nK + nN <= 11 and nM >= 8:
         return 3
     return 2
 
