@@ -1,6 +1,6 @@
 // gfx950 kernels of the tnrcs library other than the GEMMs: slice binding,
 // tiled binary-index permutation, gathered contraction (one output per
-// thread, or split over K for few outputs), FP64 slice accumulation with the
+// thread, output tiles for short sums, or split over K for few outputs), FP64 slice accumulation with the
 // numeric-range checks of scaled storage, and FP64 reductions.  Every data
 // kernel is templated on the storage element: complex64, or an FP16 / BF16
 // pair holding value * 2^-e for a per-tensor exponent e.
@@ -364,8 +364,76 @@ __global__ __launch_bounds__(256) void k_generic(const E* __restrict__ A, const 
   record_max(maxslot, mx);
 }
 
+// Short sums into many outputs (2^nM, 2^nN >= 64, 2^nK <= 16): a workgroup
+// owns a 64 x 64 output tile, gathers the tile's A rows (64 x 2^nK) and B
+// rows once into LDS in FP32, and each thread accumulates a 4 x 4 block of
+// outputs from LDS; 16 consecutive threads write 16 consecutive n of a row.
+template <typename E>
+__global__ __launch_bounds__(256) void k_generic_tiled(const E* __restrict__ A, const E* __restrict__ B,
+                                                      E* __restrict__ C, const IndexOp op, float* maxslot) {
+  __shared__ float2 As[16][65], Bs[16][65];  // [k][m], [k][n]
+  const int nk = 1 << op.nK;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int64_t tiles_n = (int64_t)1 << (op.nN - 6), tiles = (int64_t)1 << (op.nM + op.nN - 12);
+  float mx = 0.f;
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t m0 = (t / tiles_n) << 6, n0 = (t % tiles_n) << 6;
+    for (int i = tid; i < 64 * nk; i += 256) {
+      const int k = i >> 6, r = i & 63;
+      const uint64_t ak = dep((uint64_t)k, op.aK), bk = dep((uint64_t)k, op.bK);
+      As[k][r] = to_f2(A[dep((uint64_t)(m0 + r), op.aM) | ak]);
+      Bs[k][r] = to_f2(B[dep((uint64_t)(n0 + r), op.bN) | bk]);
+    }
+    __syncthreads();
+    float re[4][4], im[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) re[i][j] = im[i][j] = 0.f;
+    for (int k = 0; k < nk; ++k) {
+      float2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[i][j] = fmaf(a[i].x, b[j].x, re[i][j]);
+          re[i][j] = fmaf(-a[i].y, b[j].y, re[i][j]);
+          im[i][j] = fmaf(a[i].x, b[j].y, im[i][j]);
+          im[i][j] = fmaf(a[i].y, b[j].x, im[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        mx = mag_max(mx, re[i][j], im[i][j]);
+        const int64_t c = ((m0 + ty + 16 * i) << op.nN) | (n0 + tx + 16 * j);
+        C[c] = from_f2<E>(re[i][j] * op.out_scale, im[i][j] * op.out_scale);
+      }
+    __syncthreads();
+  }
+  record_max(maxslot, mx);
+}
+
 hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
                           hipStream_t s) {
+  if (op.nM >= 6 && op.nN >= 6 && op.nK <= 4) {
+    const dim3 g((unsigned)std::min<int64_t>((int64_t)1 << (op.nM + op.nN - 12), 16384));
+    if (dtype == TN_DTYPE_F16S)
+      hipLaunchKernelGGL(k_generic_tiled<cf16>, g, dim3(256), 0, s, (const cf16*)A, (const cf16*)B, (cf16*)C, op,
+                         maxslot);
+    else if (dtype == TN_DTYPE_BF16S)
+      hipLaunchKernelGGL(k_generic_tiled<cbf16>, g, dim3(256), 0, s, (const cbf16*)A, (const cbf16*)B, (cbf16*)C, op,
+                         maxslot);
+    else
+      hipLaunchKernelGGL(k_generic_tiled<float2>, g, dim3(256), 0, s, (const float2*)A, (const float2*)B,
+                         (float2*)C, op, maxslot);
+    return hipGetLastError();
+  }
   const int64_t nC = (int64_t)1 << (op.nM + op.nN);
   const int64_t grid = std::min<int64_t>((nC + 255) / 256, 16384);
   const dim3 g((unsigned)grid);

@@ -40,6 +40,13 @@ CASES = [
      list(range(8)) + [410, 411, 412, 413]),
 ]
 SKEWED = CASES[-6:]
+# gathered with output tiles (both free extents >= 64, at most 16 terms): an
+# outer product, and K = 4 with the operands' bits interleaved
+TILED = [
+    (list(range(7)), list(range(20, 27)), list(range(7)) + list(range(20, 27))),
+    ([0, 500, 1, 2, 501, 3, 4, 5, 6, 7], [30, 500, 31, 32, 33, 501, 34, 35], list(range(8)) + list(range(30, 36))),
+]
+CASES = CASES + TILED
 
 
 def _rand(rng, r):
@@ -71,6 +78,15 @@ def test_pair_dryrun(la, lb, lc):
 def test_pair_skewed_cases_plan_the_skewed_kernel(la, lb, lc):
     pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
     assert [o["kind"] for o in pp.json()["ops"]] == [3]
+    pp.close()
+
+
+@pytest.mark.parametrize("la,lb,lc", TILED)
+def test_pair_tiled_cases_plan_the_gathered_kernel(la, lb, lc):
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+    ops = pp.json()["ops"]
+    g = [o for o in ops if o["kind"] == 2]
+    assert len(g) == 1 and g[0]["nM"] >= 6 and g[0]["nN"] >= 6 and g[0]["nK"] <= 4
     pp.close()
 
 
