@@ -727,27 +727,67 @@ int build_plan(PlanCore& P, std::string& err) {
       g.idx.nM = nM;
       g.idx.nN = nN;
       g.idx.nK = nK;
+      // split-K: consecutive threads take consecutive k, so an operand whose
+      // lowest k bits are not its lowest bits (in order) is gathered across
+      // the whole tensor; such an operand (of 2^12 entries or more) is first
+      // permuted to [free wires, K]
+      int tmp[2] = {-1, -1};
+      std::vector<int> lay2[2] = {La, Lb};
+      if (splitk) {
+        for (int side = 0; side < 2; ++side) {
+          const std::vector<int>& have = side ? Lb : La;
+          const int r = (int)have.size();
+          bool aligned = true;
+          for (int i = 0; i < std::min(nK, 8); ++i) aligned &= pos_in(have, K[nK - 1 - i]) == i;
+          if (aligned || r < 12) continue;
+          std::vector<int> want = side ? NB : MA;
+          want.insert(want.end(), K.begin(), K.end());
+          Op op;
+          op.kind = kOpPermute;
+          op.step = t;
+          op.perm.rank = r;
+          for (int q = 0; q < r; ++q) op.perm.perm[q] = pos_in(have, want[r - 1 - q]);
+          const int opi = (int)P.ops.size();
+          op.a = operand_ref(side ? ib : ia, opi, 0);
+          Buf tb{(int64_t)1 << r, dstep, dstep, -1, (int)bufs.size()};
+          tmp[side] = (int)bufs.size();
+          bufs.push_back(tb);
+          fix.push_back({opi, 2, tmp[side]});
+          op.bytes = 2.0 * eb * std::ldexp(1.0, r);
+          P.ops.push_back(op);
+          P.stats.n_permute++;
+          lay2[side] = want;
+        }
+      }
+      const std::vector<int>& LA = lay2[0];
+      const std::vector<int>& LB = lay2[1];
       std::vector<int> p;
       bool ok = true;
       p.clear();
-      for (int i = 0; i < nM; ++i) p.push_back(pos_in(La, MA[nM - 1 - i]));
+      for (int i = 0; i < nM; ++i) p.push_back(pos_in(LA, MA[nM - 1 - i]));
       ok &= make_runs(p, &g.idx.aM);
       p.clear();
-      for (int i = 0; i < nK; ++i) p.push_back(pos_in(La, K[nK - 1 - i]));
+      for (int i = 0; i < nK; ++i) p.push_back(pos_in(LA, K[nK - 1 - i]));
       ok &= make_runs(p, &g.idx.aK);
       p.clear();
-      for (int i = 0; i < nN; ++i) p.push_back(pos_in(Lb, NB[nN - 1 - i]));
+      for (int i = 0; i < nN; ++i) p.push_back(pos_in(LB, NB[nN - 1 - i]));
       ok &= make_runs(p, &g.idx.bN);
       p.clear();
-      for (int i = 0; i < nK; ++i) p.push_back(pos_in(Lb, K[nK - 1 - i]));
+      for (int i = 0; i < nK; ++i) p.push_back(pos_in(LB, K[nK - 1 - i]));
       ok &= make_runs(p, &g.idx.bK);
       if (!ok) {
         err = "index map too fragmented";
         return TN_E_UNSUPPORTED;
       }
       int gi = (int)P.ops.size();
-      g.a = operand_ref(ia, gi, 0);
-      g.b = operand_ref(ib, gi, 1);
+      if (tmp[0] >= 0)
+        fix.push_back({gi, 0, tmp[0]});
+      else
+        g.a = operand_ref(ia, gi, 0);
+      if (tmp[1] >= 0)
+        fix.push_back({gi, 1, tmp[1]});
+      else
+        g.b = operand_ref(ib, gi, 1);
       fix.push_back({gi, 2, cbuf});
       if (splitk) {
         Buf wb{(splitk_grid(nK) << (nM + nN)) * f2, dstep, dstep, -1, (int)bufs.size()};
