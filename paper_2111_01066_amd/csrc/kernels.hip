@@ -686,25 +686,36 @@ __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, co
       }
     }
   }
+  // block sum in a fixed order: butterfly within each wave, then the four
+  // wave sums in wave order (one barrier for all outputs)
+  const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     if (i < nm) {
 #pragma unroll
       for (int j = 0; j < NN; ++j) {
-        red[0][tid] = acc_r[i][j];
-        red[1][tid] = acc_i[i][j];
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-          if (tid < w) {
-            red[0][tid] += red[0][tid + w];
-            red[1][tid] += red[1][tid + w];
-          }
-          __syncthreads();
+        float r = acc_r[i][j], q = acc_i[i][j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          r += __shfl_xor(r, o);
+          q += __shfl_xor(q, o);
         }
-        if (tid == 0) part[(int64_t)blockIdx.x * (nm * NN) + i * NN + j] = make_float2(red[0][0], red[1][0]);
-        __syncthreads();
+        if (lane == 0) {
+          red[0][wave * 64 + i * NN + j] = r;
+          red[1][wave * 64 + i * NN + j] = q;
+        }
       }
     }
+  }
+  __syncthreads();
+  const int nout = nm * NN;
+  if (tid < nout) {
+    float r = 0.f, q = 0.f;
+    for (int w = 0; w < 4; ++w) {
+      r += red[0][w * 64 + tid];
+      q += red[1][w * 64 + tid];
+    }
+    part[(int64_t)blockIdx.x * nout + tid] = make_float2(r, q);
   }
 }
 
