@@ -391,8 +391,13 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
         need = max(need, dry.info()["arena_bytes"])
         dry.close()
     arena = torch.empty(need, dtype=torch.uint8, device="cuda")
-    plans = [tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, arena=arena, tune=True,
-                        tune_db=tune_db) for w in wl]
+    plans = []
+    for i, w in enumerate(wl):
+        plans.append(tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, arena=arena,
+                                tune=True, tune_db=tune_db))
+        if (i + 1) % 32 == 0 or i + 1 == len(wl):
+            log(f"[bench] batch: {i + 1}/{len(wl)} circuits planned, tuned and calibrated "
+                f"({time.perf_counter() - t0:.1f} s)")
     t_plan = time.perf_counter() - t0
     infos = [p.info() for p in plans]
     n_sl = [i["n_slices"] for i in infos]
