@@ -430,8 +430,8 @@ static int time_class(const PlanCore& P, const std::vector<int>& a, const std::v
   };
   float t1 = 0.f, tr = 0.f;
   rc = run(1, &t1);
-  // repeat to about 2 ms of work (3 to 20 runs)
-  const int reps = std::max(3, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
+  // repeat to about 2 ms of work (at most 20 runs)
+  const int reps = std::max(1, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
   if (!rc) rc = run(reps, &tr);
   cleanup();
   if (!rc) *ms = tr / reps;

@@ -136,8 +136,8 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t1, e0, e1);
-    // repeat to about 2 ms of work (3 to 20 runs)
-    const int reps = std::max(3, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
+    // repeat to about 2 ms of work (at most 20 runs)
+    const int reps = std::max(1, std::min(20, (int)std::ceil(2.0 / std::max(t1, 1e-3f))));
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
     for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(v);
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
