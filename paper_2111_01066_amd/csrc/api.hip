@@ -1084,7 +1084,7 @@ int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t 
   if (dtype != TN_DTYPE_F16S && dtype != TN_DTYPE_BF16S) return fail(TN_E_ARG, "dtype must be F16S or BF16S");
   if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
   if (!hgemm_shape_ok(M, N, K) || batch < 0 || batch > 65535)
-    return fail(TN_E_ARG, "shape not supported: M, N multiples of 128, K a multiple of 16");
+    return fail(TN_E_ARG, "shape not supported: M, N multiples of 64, K a multiple of 16");
   if (splits > 1 && (!work || batch != 1 || K % (16 * (int64_t)splits)))
     return fail(TN_E_ARG, "split-K needs work, batch 1 and K a multiple of 16*splits");
   hipError_t e = launch_gemm_half(dtype, A, B, C, M, N, K, batch, form, (hipStream_t)stream, (float2*)work,
