@@ -46,7 +46,11 @@ TILED = [
     (list(range(7)), list(range(20, 27)), list(range(7)) + list(range(20, 27))),
     ([0, 500, 1, 2, 501, 3, 4, 5, 6, 7], [30, 500, 31, 32, 33, 501, 34, 35], list(range(8)) + list(range(30, 36))),
 ]
-CASES = CASES + TILED
+# split-K whose B holds the contracted wires in another order: B is first
+# permuted to [free wires, K] so that consecutive k are adjacent in memory
+ALIGN = [([20, 21, 22] + list(range(12)), [30, 31, 32] + [5, 0, 9, 2, 11, 7, 1, 4, 10, 3, 8, 6],
+          [20, 21, 22, 30, 31, 32])]
+CASES = CASES + TILED + ALIGN
 
 
 def _rand(rng, r):
@@ -87,6 +91,17 @@ def test_pair_tiled_cases_plan_the_gathered_kernel(la, lb, lc):
     ops = pp.json()["ops"]
     g = [o for o in ops if o["kind"] == 2]
     assert len(g) == 1 and g[0]["nM"] >= 6 and g[0]["nN"] >= 6 and g[0]["nK"] <= 4
+    pp.close()
+
+
+@pytest.mark.parametrize("la,lb,lc", ALIGN)
+def test_pair_splitk_aligns_scattered_operand(la, lb, lc):
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+    ops = pp.json()["ops"]
+    assert [o["kind"] for o in ops] == [0, 4]  # a permute of B, then split-K
+    assert ops[0]["a"] == [4, 0]  # the caller's B
+    run = ops[1]["bK"][0]
+    assert run[0] == 0 and run[1] == 0 and run[2] == 12  # all 12 k bits low and in order
     pp.close()
 
 
