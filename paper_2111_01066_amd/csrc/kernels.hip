@@ -631,7 +631,24 @@ hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const
 // K bits are the operands' low bits), the block reduces in LDS, and one
 // block sums the FP32 per-block partials in a fixed order.
 
-template <int NN, typename E>
+// VK consecutive entries starting at p (VK > 1: one 16-byte load).
+template <int VK, typename E>
+__device__ __forceinline__ void load_run(const E* p, float2 (&out)[VK]) {
+  if constexpr (VK == 1) {
+    out[0] = to_f2(*p);
+  } else {
+    static_assert(VK * sizeof(E) == 16, "one 16-byte load");
+    const row_u32x4 w = *reinterpret_cast<const row_u32x4*>(p);
+    E v[VK];
+    __builtin_memcpy(v, &w, 16);
+#pragma unroll
+    for (int i = 0; i < VK; ++i) out[i] = to_f2(v[i]);
+  }
+}
+
+// VK > 1: each thread takes VK consecutive k per step (both operands' lowest
+// log2(VK) k bits are their lowest bits, in order), read in 16-byte loads.
+template <int NN, int VK, typename E>
 __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, const E* __restrict__ B,
                                                     float2* __restrict__ part, const IndexOp op) {
   // outputs (m, n): m < nm = 2^nM <= 64 / NN, n < NN = 2^nN; each k loads
@@ -649,40 +666,49 @@ __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, co
   for (int i = 0; i < NM; ++i)
 #pragma unroll
     for (int j = 0; j < NN; ++j) acc_r[i][j] = acc_i[i][j] = 0.f;
+  auto madd = [&](int i, int j, const float2 x, const float2 y) {
+    acc_r[i][j] = fmaf(x.x, y.x, acc_r[i][j]);
+    acc_r[i][j] = fmaf(-x.y, y.y, acc_r[i][j]);
+    acc_i[i][j] = fmaf(x.x, y.y, acc_i[i][j]);
+    acc_i[i][j] = fmaf(x.y, y.x, acc_i[i][j]);
+  };
   const int64_t nK = (int64_t)1 << op.nK;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + tid; k < nK; k += (int64_t)gridDim.x * 256) {
+  for (int64_t k = ((int64_t)blockIdx.x * 256 + tid) * VK; k < nK; k += (int64_t)gridDim.x * 256 * VK) {
     const uint64_t ak = dep((uint64_t)k, op.aK), bk = dep((uint64_t)k, op.bK);
     if constexpr (NN <= 8) {  // keep the B entries, stream the A entries
-      float2 y[NN];
+      float2 y[NN][VK];
 #pragma unroll
-      for (int j = 0; j < NN; ++j) y[j] = to_f2(B[bn[j] | bk]);
+      for (int j = 0; j < NN; ++j) load_run<VK>(B + (bn[j] | bk), y[j]);
 #pragma unroll
       for (int i = 0; i < NM; ++i) {
         if (i < nm) {  // uniform across the grid
-          const float2 x = to_f2(A[am[i] | ak]);
+          float2 x[VK];
+          load_run<VK>(A + (am[i] | ak), x);
 #pragma unroll
-          for (int j = 0; j < NN; ++j) {
-            acc_r[i][j] = fmaf(x.x, y[j].x, acc_r[i][j]);
-            acc_r[i][j] = fmaf(-x.y, y[j].y, acc_r[i][j]);
-            acc_i[i][j] = fmaf(x.x, y[j].y, acc_i[i][j]);
-            acc_i[i][j] = fmaf(x.y, y[j].x, acc_i[i][j]);
-          }
+          for (int v = 0; v < VK; ++v)
+#pragma unroll
+            for (int j = 0; j < NN; ++j) madd(i, j, x[v], y[j][v]);
         }
       }
     } else {  // few m (NM <= 4): keep the A entries, stream the B entries
-      float2 x[NM];
+      float2 x[NM][VK];
 #pragma unroll
-      for (int i = 0; i < NM; ++i) x[i] = i < nm ? to_f2(A[am[i] | ak]) : make_float2(0.f, 0.f);
+      for (int i = 0; i < NM; ++i) {
+        if (i < nm) {
+          load_run<VK>(A + (am[i] | ak), x[i]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VK; ++v) x[i][v] = make_float2(0.f, 0.f);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < NN; ++j) {
-        const float2 y = to_f2(B[bn[j] | bk]);
+        float2 y[VK];
+        load_run<VK>(B + (bn[j] | bk), y);
 #pragma unroll
-        for (int i = 0; i < NM; ++i) {
-          acc_r[i][j] = fmaf(x[i].x, y.x, acc_r[i][j]);
-          acc_r[i][j] = fmaf(-x[i].y, y.y, acc_r[i][j]);
-          acc_i[i][j] = fmaf(x[i].x, y.y, acc_i[i][j]);
-          acc_i[i][j] = fmaf(x[i].y, y.x, acc_i[i][j]);
-        }
+        for (int v = 0; v < VK; ++v)
+#pragma unroll
+          for (int i = 0; i < NM; ++i) madd(i, j, x[i][v], y[v]);
       }
     }
   }
@@ -753,21 +779,32 @@ __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__
 
 int64_t splitk_blocks(const IndexOp& op) { return splitk_grid(op.nK); }
 
+template <int VK, typename E>
+static void launch_splitk_v(const E* A, const E* B, float2* part, const IndexOp& op, dim3 grid, hipStream_t s) {
+  const dim3 blk(256);
+  switch (op.nN) {
+    case 0: hipLaunchKernelGGL((k_splitk_part<1, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 1: hipLaunchKernelGGL((k_splitk_part<2, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 2: hipLaunchKernelGGL((k_splitk_part<4, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 3: hipLaunchKernelGGL((k_splitk_part<8, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 4: hipLaunchKernelGGL((k_splitk_part<16, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 5: hipLaunchKernelGGL((k_splitk_part<32, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    default: hipLaunchKernelGGL((k_splitk_part<64, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+  }
+}
+
 template <typename E>
 static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const IndexOp& op, float* maxslot,
                             hipStream_t s) {
   const int nout = 1 << (op.nM + op.nN);
   const int64_t g = splitk_blocks(op);
-  const dim3 grid((unsigned)g), blk(256);
-  switch (op.nN) {
-    case 0: hipLaunchKernelGGL((k_splitk_part<1, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 1: hipLaunchKernelGGL((k_splitk_part<2, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 2: hipLaunchKernelGGL((k_splitk_part<4, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 3: hipLaunchKernelGGL((k_splitk_part<8, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 4: hipLaunchKernelGGL((k_splitk_part<16, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 5: hipLaunchKernelGGL((k_splitk_part<32, E>), grid, blk, 0, s, A, B, part, op); break;
-    default: hipLaunchKernelGGL((k_splitk_part<64, E>), grid, blk, 0, s, A, B, part, op); break;
-  }
+  // 16-byte runs of k when both operands hold their lowest k bits lowest
+  constexpr int VK = 16 / (int)sizeof(E), LV = VK == 4 ? 2 : 1;
+  auto low = [&](const Runs& r) { return r.n >= 1 && r.src[0] == 0 && r.dst[0] == 0 && r.len[0] >= LV; };
+  if (op.nK >= LV && low(op.aK) && low(op.bK))
+    launch_splitk_v<VK>(A, B, part, op, dim3((unsigned)g), s);
+  else
+    launch_splitk_v<1>(A, B, part, op, dim3((unsigned)g), s);
   hipLaunchKernelGGL(k_splitk_final<E>, dim3(1), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot);
 }
 
