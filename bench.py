@@ -375,6 +375,58 @@ def crosscheck_30q(tnrcs, torch, np):
     return out
 
 
+def oracle_timings(tnrcs, torch, np, c2_kernels):
+    """The oracle (FP64 NumPy on all host threads) on the small workloads,
+    beside the GPU on the same work: config 1's state vector and its
+    unsliced pairwise contraction (all 2^20 amplitudes, the GPU plan in
+    complex64), and one full config-2 pair (rank 27 x rank 25, about
+    8.8e12 flop; the GPU figure is one pair's share of the 32-pair launch).
+    Reported baselines, not targets."""
+    import oracle
+    from oracle.tn import contract_network, pairwise_contract
+    from rqcgen.workloads import config1, config2_pair
+    out = {"cores": len(os.sched_getaffinity(0))}
+    w = config1()
+    t0 = time.perf_counter()
+    oracle.statevector(w.circuit)
+    t_sv = time.perf_counter() - t0
+    leaves, ow = oracle.build_network(w.circuit, w.open_qubits, w.out_bits)
+    t0 = time.perf_counter()
+    contract_network(leaves, w.pairs, ow)
+    t_tn = time.perf_counter() - t0
+    plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits)
+    amp = torch.zeros(1 << 20, dtype=torch.complex128, device="cuda")
+    plan.contract(0, 1, amp)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        plan.contract(0, 1, amp)
+    e1.record()
+    torch.cuda.synchronize()
+    t_gpu = e0.elapsed_time(e1) / 5e3
+    plan.close()
+    out["config1_20q_all_open"] = {"oracle_statevector_s": t_sv, "oracle_tn_s": t_tn, "gpu_c64_s": t_gpu,
+                                   "speedup_vs_oracle_tn": t_tn / t_gpu}
+    log(f"[bench] oracle, config 1: state vector {t_sv:.2f} s, pairwise contraction {t_tn:.2f} s; "
+        f"GPU complex64 {t_gpu * 1e3:.2f} ms")
+    la, lb, lc = config2_pair(seed=2)
+    rng = np.random.default_rng(2)
+    A = ((rng.standard_normal(1 << 27) + 1j * rng.standard_normal(1 << 27)) * np.sqrt(0.5)).reshape((2,) * 27)
+    B = ((rng.standard_normal(1 << 25) + 1j * rng.standard_normal(1 << 25)) * np.sqrt(0.5)).reshape((2,) * 25)
+    t0 = time.perf_counter()
+    C, _ = pairwise_contract(A, la, B, lb)
+    t_pair = time.perf_counter() - t0
+    del A, B, C
+    g = c2_kernels.get("pairs_rank27x25_c64", {})
+    gpu_pair = g.get("ms_per_launch", float("nan")) / g.get("pairs_per_launch", 1) / 1e3
+    out["config2_pair"] = {"oracle_s": t_pair, "oracle_complex_tflops": 8.0 * 2 ** 40 / t_pair / 1e12,
+                           "gpu_c64_s_per_pair": gpu_pair, "speedup": t_pair / gpu_pair}
+    log(f"[bench] oracle, config 2: one pair in {t_pair:.1f} s ({8.0 * 2 ** 40 / t_pair / 1e12:.2f} complex "
+        f"TFLOP/s); GPU complex64 {gpu_pair * 1e3:.1f} ms per pair")
+    return out
+
+
 def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
     """Config 5: the frozen uneven circuits whose order costs at most `cap`
     flops over all slices, one 64-amplitude bunch each, scaled storage,
@@ -534,6 +586,7 @@ def main():
             torch.cuda.empty_cache()
         extra["precision"] = prec
         extra["kernels"] = micro(tnrcs, torch, np)
+        extra["oracle_timings"] = oracle_timings(tnrcs, torch, np, extra["kernels"])
         extra["batch_uneven"] = batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")
         extra["crosscheck_30q"] = crosscheck_30q(tnrcs, torch, np)
 
