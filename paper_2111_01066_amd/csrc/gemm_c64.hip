@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "elem.h"
 #include "kernels.h"
@@ -23,7 +24,8 @@ constexpr int GBM = 64, GBN = 64, GBK = 16;
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, const float2* __restrict__ B,
-                                              float2* __restrict__ C, int64_t M, int64_t N, int64_t K) {
+                                              float2* __restrict__ C, int64_t M, int64_t N, int64_t K,
+                                              int chunk) {
   __shared__ float As[2][GBK][GBM + 4];
   __shared__ float Bs[2][GBK][GBN + 4];
   const int tid = threadIdx.x;
@@ -38,7 +40,43 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
   const float2* Ap = A + (bm + lrow) * K + lk;
   const float2* Bp = B + (bn + lrow) * K + lk;
-  for (int64_t k0 = 0; k0 < K; k0 += GBK) {
+  const int j = lane & 31;
+  // adds (ADD false: stores) the running FP32 sums to C and restarts them
+  auto flush = [&](auto add) {
+    constexpr bool ADD = decltype(add)::value;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      float2 v;
+      if (FORM == TN_GEMM_3M) {
+        v.x = c0[r] - c1[r];
+        v.y = c2[r] - c0[r] - c1[r];
+      } else {
+        v.x = c0[r];
+        v.y = c1[r];
+      }
+      float2* p = C + (bm + wm + i) * N + bn + wn + j;
+      if constexpr (ADD) {
+        const float2 o = *p;
+        v.x += o.x;
+        v.y += o.y;
+      }
+      *p = v;
+    }
+    c0 = floatx16{};
+    c1 = floatx16{};
+    c2 = floatx16{};
+  };
+  bool first = true;
+  int it = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += GBK, ++it) {
+    if (chunk > 0 && it > 0 && it % chunk == 0) {
+      if (first)
+        flush(std::false_type{});
+      else
+        flush(std::true_type{});
+      first = false;
+    }
     const float4 a01 = *reinterpret_cast<const float4*>(Ap + k0);
     const float4 a23 = *reinterpret_cast<const float4*>(Ap + k0 + 2);
     const float4 b01 = *reinterpret_cast<const float4*>(Bp + k0);
@@ -80,20 +118,10 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
     }
     __syncthreads();
   }
-  const int j = lane & 31;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    float2 v;
-    if (FORM == TN_GEMM_3M) {
-      v.x = c0[r] - c1[r];
-      v.y = c2[r] - c0[r] - c1[r];
-    } else {
-      v.x = c0[r];
-      v.y = c1[r];
-    }
-    C[(bm + wm + i) * N + bn + wn + j] = v;
-  }
+  if (first)
+    flush(std::false_type{});
+  else
+    flush(std::true_type{});
 }
 
 // 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32 MFMA
@@ -106,7 +134,8 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
 template <int FORM>
 __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
                                                  float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
-                                                 int64_t sA, int64_t sB, int64_t sC, int64_t Mt, int64_t Nt) {
+                                                 int64_t sA, int64_t sB, int64_t sC, int64_t Mt, int64_t Nt,
+                                                 int chunk) {
   constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
   constexpr int BM = 128, BN = 128, BK = 16, LD = BM + 2;
   __shared__ float As[2][BK][LD];
@@ -136,7 +165,47 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
     rb[j] = *reinterpret_cast<const float4*>(Bp + 2 * j);
   }
   const int c = lane & 31, kh = lane >> 5;
-  for (int64_t k0 = 0; k0 < k_len; k0 += BK) {
+  // Adds (ADD false: stores) the running FP32 sums to C and restarts them.
+  // Called every `chunk` K stages, where the staged operands have just been
+  // written to LDS and the prefetch registers are free, so one FP32
+  // accumulation chain covers at most chunk * BK terms.
+  auto flush = [&](auto add) {
+    constexpr bool ADD = decltype(add)::value;
+    // the row stride is made opaque here so that the compiler does not keep
+    // the 64 output addresses live across the K loop
+    int64_t ld = N;
+    asm volatile("" : "+s"(ld));
+    float2* Cw = C + (bm + wm + 4 * kh) * ld + bn + wn + c;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float2 v;
+          if (FORM == TN_GEMM_3M) {
+            v.x = acc[0][i][j][r] - acc[1][i][j][r];
+            v.y = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
+          } else {
+            v.x = acc[0][i][j][r];
+            v.y = acc[1][i][j][r];
+          }
+          float2* p = Cw + (32 * i + 8 * (r >> 2) + (r & 3)) * ld + 32 * j;
+          if constexpr (ADD) {
+            const float2 o = *p;
+            v.x += o.x;
+            v.y += o.y;
+          }
+          *p = v;
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q][i][j] = floatx16{};
+        __builtin_amdgcn_sched_barrier(0);  // one 32x32 block's loads in flight at a time
+      }
+  };
+  bool first = true;
+  int it = 0;
+  for (int64_t k0 = 0; k0 < k_len; k0 += BK, ++it) {
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -148,6 +217,13 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
       Bs[1][lk + 2 * j][lrow] = rb[j].y;
       Bs[0][lk + 2 * j + 1][lrow] = rb[j].z;
       Bs[1][lk + 2 * j + 1][lrow] = rb[j].w;
+    }
+    if (chunk > 0 && it > 0 && it % chunk == 0) {
+      if (first)
+        flush(std::false_type{});
+      else
+        flush(std::true_type{});
+      first = false;
     }
     __syncthreads();
     if (k0 + BK < k_len) {
@@ -192,37 +268,24 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
         }
     }
   }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int col = wn + 32 * j + c;
-        float2 v;
-        if (FORM == TN_GEMM_3M) {
-          v.x = acc[0][i][j][r] - acc[1][i][j][r];
-          v.y = acc[P - 1][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
-        } else {
-          v.x = acc[0][i][j][r];
-          v.y = acc[1][i][j][r];
-        }
-        C[(bm + row) * N + bn + col] = v;
-      }
+  if (first)
+    flush(std::false_type{});
+  else
+    flush(std::true_type{});
 }
 
-// C[i] = sum over slabs s (in order) of W[s][i].
+// C[i] = sum over slabs s (in order) of W[s][i], summed in FP64 and rounded
+// once.
 __global__ __launch_bounds__(256) void k_splitk_sum(const float2* __restrict__ W, float2* __restrict__ C, int64_t n,
                                                    int slabs) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float r = 0.f, im = 0.f;
+    double r = 0.0, im = 0.0;
     for (int sl = 0; sl < slabs; ++sl) {
       const float2 v = W[(int64_t)sl * n + i];
-      r += v.x;
-      im += v.y;
+      r += (double)v.x;
+      im += (double)v.y;
     }
-    C[i] = make_float2(r, im);
+    C[i] = make_float2((float)r, (float)im);
   }
 }
 
@@ -239,15 +302,18 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
   if (tile == 128 && !fits128) return hipErrorInvalidValue;
   if (tile == 64 && splits > 1) return hipErrorInvalidValue;
   const bool big = fits128 && tile != 64;
+  const int chunk = kAccChain / 16;  // K stages of the 128x128 kernel per FP32 chain
   if (splits > 1) {
     if (batch != 1 || !work || !big || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
     const int64_t kl = K / splits;
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * splits));
     if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt);
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
+                         chunk);
     else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt);
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
+                         chunk);
     const int64_t n = M * N;
     hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
                        work, C, n, splits);
@@ -260,17 +326,19 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * batch));
     if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt);
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
+                         chunk);
     else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt);
+      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
+                         chunk);
     return hipGetLastError();
   }
   if (N / GBN > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)batch);
   if (form == TN_GEMM_3M)
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
   else
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K);
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
   return hipGetLastError();
 }
 

@@ -15,6 +15,12 @@ namespace tnrcs {
 constexpr int kMaxRank = 48;  // bits of a device tensor index
 constexpr int kMaxRuns = 48;  // runs of a bit-deposit map
 constexpr int kSkinnyMaxLog2 = 11;  // the skewed kernel keeps 2^(nK+nN) <= 2^11 B entries in LDS
+// Longest run of terms that one FP32 accumulator of the complex64 GEMM sums
+// before the run is added to the output: sequential FP32 accumulation of n
+// products of random sign has a relative error growing like u sqrt(n/2)
+// (u = 2^-24), about 6e-6 for n = 2^17, so long contractions are summed in
+// runs of this length (about 8e-7 at n = 2^17).
+constexpr int kAccChain = 2048;
 
 // Bit-deposit map: value bit (src + i) goes to target bit (dst + i) for
 // i < len, for each run.  Built from "value bit j -> target position pos[j]".

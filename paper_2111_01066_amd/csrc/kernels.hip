@@ -346,17 +346,21 @@ __global__ __launch_bounds__(256) void k_generic(const E* __restrict__ A, const 
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nC; c += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t m = (uint64_t)c >> op.nN, n = (uint64_t)c & nmask;
     const uint64_t ab = dep(m, op.aM), bb = dep(n, op.bN);
+    // runs of at most 2^kTabBits terms per FP32 chain, added to the total
     float re = 0.f, im = 0.f;
     for (int64_t h = 0; h < n_hi; ++h) {
       const uint64_t ah = ab | dep((uint64_t)h << lo_bits, op.aK), bh = bb | dep((uint64_t)h << lo_bits, op.bK);
+      float pr = 0.f, pi = 0.f;
       for (int k = 0; k < n_lo; ++k) {
         const float2 x = to_f2(A[ah | atab[k]]);
         const float2 y = to_f2(B[bh | btab[k]]);
-        re = fmaf(x.x, y.x, re);
-        re = fmaf(-x.y, y.y, re);
-        im = fmaf(x.x, y.y, im);
-        im = fmaf(x.y, y.x, im);
+        pr = fmaf(x.x, y.x, pr);
+        pr = fmaf(-x.y, y.y, pr);
+        pi = fmaf(x.x, y.y, pi);
+        pi = fmaf(x.y, y.x, pi);
       }
+      re += pr;
+      im += pi;
     }
     mx = mag_max(mx, re, im);
     C[c] = from_f2<E>(re * op.out_scale, im * op.out_scale);
