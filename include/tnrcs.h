@@ -142,8 +142,10 @@ typedef struct {
  * kernel when the contraction has at most 2^6 terms; gathered, skewed and
  * split-K against each other for steps with too few outputs for the GEMM)
  * is run in each on a one-step plan of the same operand layouts over
- * scratch buffers of random values (at most a third of the free device memory;
- * larger steps keep the default rule), and the fastest is planned.  Tile:
+ * scratch buffers of random values (at most 8 GiB and a third of the free
+ * device memory; larger steps keep the default rule), and the fastest is
+ * planned.  With the environment variable TNRCS_VERBOSE set, each tuned step
+ * prints a line on stderr.  Tile:
  * for each distinct dense-GEMM shape of the plan (dtype, M, N, K, form)
  * every valid tile size, K-split count and kernel variant is timed with HIP
  * events on the plan's own buffers (the arena is filled with random values

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,6 +26,13 @@ thread_local std::string g_err;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+// Progress lines of the plan-time tuners on stderr when TNRCS_VERBOSE is set
+// (tuning a large plan runs for minutes).
+bool verbose() {
+  static const bool v = std::getenv("TNRCS_VERBOSE") != nullptr;
+  return v;
 }
 
 int hip_fail(hipError_t e, const char* what) {
@@ -337,6 +345,10 @@ static int tune_plan(tn_plan_s* p) {
     int rc = tune_gemm(P.opts.dtype, op.gemm, resolve(p, op.a), resolve(p, op.b), resolve(p, op.c), w, slot,
                        P.opts.tune_db, err);
     if (rc) return fail(rc, err);
+    if (verbose())
+      std::fprintf(stderr, "tnrcs: tuned GEMM %lld x %lld x %lld: tile %d split %d variant %d\n",
+                   (long long)op.gemm.M, (long long)op.gemm.N, (long long)op.gemm.K, op.gemm.tile, op.gemm.split_k,
+                   op.gemm.occ);
   }
   make_json(P);
   return TN_OK;
@@ -353,7 +365,7 @@ static int tune_plan(tn_plan_s* p) {
 // kClassTuneMaxBytes) keep the rule.  Choices are cached per process and in
 // the tuning database by dtype and the step's relabelled layouts.
 constexpr int kFuseMaxK = 6;
-constexpr int64_t kClassTuneMaxBytes = (int64_t)64 << 30;
+constexpr int64_t kClassTuneMaxBytes = (int64_t)8 << 30;
 
 // Average time of one run of a one-step plan's ops in class `cls` (INFINITY
 // when the step does not fit the budget); builds, runs and frees the plan.
@@ -472,6 +484,9 @@ static int tune_classes(PlanCore& P, bool measure) {
       }
       if (best < 0) continue;  // above the tuning budget: the rule stands
       class_store(P.opts.dtype, key, P.opts.tune_db, best, best_ms);
+      if (verbose())
+        std::fprintf(stderr, "tnrcs: class tuner: step %d (%d x %d x %d bits): class %d, %.3f ms\n", st.t, st.nM,
+                     st.nN, st.nK, best, best_ms);
     }
     if (!(valid & (1u << best))) continue;
     P.class_override[st.t] = best;
