@@ -324,6 +324,23 @@ int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t 
                   int64_t batch, int32_t form, float out_scale, void* work, int32_t splits, void* max_out,
                   void* stream);
 
+/* Allocation-free form of tn_cgemm_c64 with batch 1, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  With splits > 1 the K slabs go to a
+ * static device array of TN_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends (its address is looked up
+ * once per device with hipGetSymbolAddress); nothing is allocated or freed.
+ * The result is bitwise that of tn_cgemm_c64 with the same arguments (same
+ * kernels, same summation order).  Every slab is written before it is read,
+ * so nothing needs clearing between calls.  Runs on the calling thread's
+ * current device.  Errors: TN_E_ARG for the shapes tn_cgemm_c64 rejects and
+ * when splits * M * N * 8 bytes exceed the scratch (8 Mi complex64 entries,
+ * e.g. M = N = 1024 with up to 8 slabs).  Calls that overlap in time on one
+ * device share the array and race: order them on one stream. */
+#define TN_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int tn_cgemm_c64_noalloc(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K, int32_t form,
+                         int32_t splits, void* stream);
+
 /* ---- measurement probes (the machine ceilings the kernels are compared with) ---- */
 
 /* MFMA issue loop with no memory traffic: kind 0 = v_mfma_f32_32x32x2_f32,

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -1105,6 +1106,68 @@ int tn_cgemm_half(int32_t dtype, const void* A, const void* B, void* C, int64_t 
   hipError_t e = launch_gemm_half(dtype, A, B, C, M, N, K, batch, form, (hipStream_t)stream, (float2*)work,
                                   splits < 1 ? 1 : splits, out_scale, (float*)max_out);
   if (e != hipSuccess) return hip_fail(e, "half gemm kernel");
+  return TN_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free split-K GEMM: the slab workspace is a static device array ----
+
+namespace {
+
+constexpr int64_t kScratchBytes = TN_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+// Split-K slabs of tn_cgemm_c64_noalloc.  Each device holds its own copy for
+// the life of the process.  In host code this name is only a handle for
+// hipGetSymbolAddress; kernels get the per-device address below.
+static __device__ __align__(256) float2 scratch[kScratchBytes / sizeof(float2)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(TN_E_UNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(TN_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tn_cgemm_c64_noalloc(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K, int32_t form,
+                         int32_t splits, void* stream) {
+  if (!A || !B || !C) return fail(TN_E_ARG, "NULL argument");
+  if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
+  if (!gemm_shape_ok(M, N, K)) return fail(TN_E_ARG, "shape not supported: M, N multiples of 64, K a multiple of 16");
+  if (splits < 1) splits = 1;
+  void* work = nullptr;
+  if (splits > 1) {
+    if (M % 128 || N % 128 || K % (16 * (int64_t)splits))
+      return fail(TN_E_ARG, "split-K needs M and N multiples of 128 and K a multiple of 16*splits");
+    const int64_t need = (int64_t)splits * M * N * (int64_t)sizeof(float2);
+    if (need > kScratchBytes)
+      return fail(TN_E_ARG, "split-K slabs need " + std::to_string(need) + " bytes; the static scratch holds " +
+                                std::to_string(kScratchBytes) + " (splits * M * N <= " +
+                                std::to_string(kScratchBytes / 8) + ")");
+    int rc = scratch_address(&work);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_gemm_c64((const float2*)A, (const float2*)B, (float2*)C, M, N, K, 1, form,
+                                 (hipStream_t)stream, (float2*)work, splits);
+  if (e != hipSuccess) return hip_fail(e, "gemm kernel");
   return TN_OK;
 }
 

@@ -91,6 +91,8 @@ _lib.tn_cgemm_half.argtypes = [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c
                                ctypes.c_float, c_void_p, c_int32, c_void_p, c_void_p]
 _lib.tn_cgemm_c64.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int64, c_int32,
                               c_void_p, c_int32, c_void_p]
+_lib.tn_cgemm_c64_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int32, c_int32,
+                                         c_void_p]
 _lib.tn_contract_slices_checked.argtypes = [c_void_p, c_int64, c_int64, c_void_p, c_void_p, POINTER(c_int32)]
 _lib.tn_plan_shift_outputs.argtypes = [c_void_p, c_int32, c_int32]
 _lib.tn_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_int64), POINTER(c_void_p), POINTER(c_void_p)]
@@ -109,7 +111,7 @@ _lib.tn_amp_hist.argtypes = [c_void_p, c_int64, c_double, c_double, c_int32, c_v
 EXPORTED = ["tn_plan_opts_default", "tn_plan", "tn_contract_slices", "tn_plan_info", "tn_plan_json",
             "tn_plan_leaf", "tn_plan_status", "tn_plan_profile", "tn_plan_set_output_bits", "tn_plan_destroy", "tn_last_error", "tn_pair_plan", "tn_pair_run",
             "tn_contract_slices_checked", "tn_plan_shift_outputs", "tn_batch_create", "tn_batch_run", "tn_batch_destroy", "tn_contract_batch",
-            "tn_probe_mfma", "tn_probe_mfma_out_floats", "tn_probe_copy", "tn_permute", "tn_cgemm_c64", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_frugal", "tn_amp_hist"]
+            "tn_probe_mfma", "tn_probe_mfma_out_floats", "tn_probe_copy", "tn_permute", "tn_cgemm_c64", "tn_cgemm_c64_noalloc", "tn_cgemm_half", "tn_amp_norm2", "tn_amp_xeb", "tn_amp_frugal", "tn_amp_hist"]
 
 
 def _check(rc: int):
@@ -385,6 +387,11 @@ def tn_cgemm_c64(A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4
     _check(_lib.tn_cgemm_c64(c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(M), int(N), int(K),
                              int(batch), GEMM_FORMS[form], c_void_p(_ptr(work) if work is not None else None),
                              int(splits), c_void_p(_stream(stream))))
+
+
+def tn_cgemm_c64_noalloc(A, B, C, M: int, N: int, K: int, form: str = "4m", splits: int = 1, stream=None):
+    _check(_lib.tn_cgemm_c64_noalloc(c_void_p(_ptr(A)), c_void_p(_ptr(B)), c_void_p(_ptr(C)), int(M), int(N), int(K),
+                                     GEMM_FORMS[form], int(splits), c_void_p(_stream(stream))))
 
 
 def tn_cgemm_half(dtype: str, A, B, C, M: int, N: int, K: int, batch: int = 1, form: str = "4m",
