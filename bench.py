@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "sec/slice + complex TFLOP/s (% MFMA peak), 53-qubit 14-cycle synthetic RCS"
 PEAK = {"c64": 157.3, "f16s": 2500.0, "bf16s": 2500.0}  # dense MFMA TFLOP/s: FP32, FP16, BF16
 PEAK_HBM = 8000.0  # GB/s
-KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 4: "k_splitk", 9: "k_accum"}
+KIND_NAMES = {0: "k_permute", 1: "k_cgemm", 2: "k_generic", 3: "k_skinny", 4: "k_splitk", 5: "k_skew", 9: "k_accum"}
 
 
 def log(*a):
@@ -142,7 +142,7 @@ def kernel_split(res, dtype):
         d["issued"] += o["flops"] * (0.75 if o.get("form") == 2 else 1.0)
     split = {KIND_NAMES[k]: {"ms_per_slice": v["ms"], "launches": v["n"]} for k, v in by_kind.items()}
     for k, v in by_kind.items():
-        if k in (0, 2, 3, 4) and v["ms"] > 0:
+        if k in (0, 2, 3, 4, 5) and v["ms"] > 0:
             split[KIND_NAMES[k]]["GB/s"] = v["bytes"] / (v["ms"] / 1e3) / 1e9
     order = sorted(range(len(ops)), key=lambda i: -ms[i])
     for i in order[:12]:
@@ -290,7 +290,7 @@ def micro(tnrcs, torch, np):
         fl = 8.0 * 2 ** 15 * 2 ** 13 * 2 ** 12 * n_pairs
         tf = fl / ms / 1e9
         out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
-                                          "frac_peak": tf / PEAK[dtype]}
+                                          "complex_rate_over_dtype_mfma_peak": tf / PEAK[dtype]}
         log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
             f"TFLOP/s ({tf / PEAK[dtype]:.1%} of the {dtype} MFMA peak, permutes included)")
         pp.close()
@@ -508,7 +508,7 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=0, help="slices timed (0: every slice of the bunch)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="auto", choices=["auto", "4m", "3m"])
     ap.add_argument("--dtype", default="c64", choices=["c64", "f16s", "bf16s"])
@@ -545,7 +545,8 @@ def main():
     w = config3()
     log(f"[bench] workload {w.name}: {len(w.pairs)} steps, k={len(w.sliced)} sliced wires")
     n_slices = 1 << len(w.sliced)
-    K, W = min(args.steps, n_slices - args.warmup), args.warmup
+    K = n_slices if args.steps <= 0 else min(args.steps, n_slices)
+    W = args.warmup
     main_res = run_network(tnrcs, torch, w, args.dtype, args.form, K, W, graph=not args.no_graph,
                            tune=not args.no_tune, tune_db=args.tune_db)
     by_kind, split = kernel_split(main_res, args.dtype)
@@ -615,9 +616,12 @@ def main():
                         "6 open qubits (64-amplitude bunch), per-slice tensors <= 2^32 entries",
             "sec_per_slice": sec,
             "complex_tflops": main_res["tflops"],
-            "frac_mfma_peak": main_res["tflops"] / PEAK[args.dtype],
+            "complex_tflops_over_dtype_mfma_peak": main_res["tflops"] / PEAK[args.dtype],
             "n_slices_total": n_slices,
-            "extrapolated_total_s": sec * n_slices,
+            "slices_timed": K,
+            "time_to_amplitudes_s": sec * n_slices,
+            "time_to_amplitudes_note": ("all slices of the bunch timed" if K == n_slices else
+                                        f"{K} of {n_slices} slices timed, time per slice x slice count"),
             "flops_per_slice": info["flops_per_slice"],
             "bytes_per_slice": info["bytes_per_slice"],
             "gemm_form": args.form,

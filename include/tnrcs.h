@@ -139,8 +139,9 @@ typedef struct {
  *
  * Tuning (opts->tune), two stages.  Kernel class: a step with more than
  * one valid kernel class (permutes + MFMA GEMM against the fused gathered
- * kernel when the contraction has at most 2^6 terms; gathered, skewed and
- * split-K against each other for steps with too few outputs for the GEMM)
+ * kernel and the matrix-core skewed kernel when the contraction has at most
+ * 2^6 terms; gathered, the two skewed kernels and split-K against each
+ * other for steps with too few outputs for the GEMM)
  * is run in each on a one-step plan of the same operand layouts over
  * scratch buffers of random values (at most 8 GiB and a third of the free
  * device memory; larger steps keep the default rule), and the fastest is
@@ -173,7 +174,10 @@ int tn_plan(const tn_circuit* c, const int32_t* order_pairs, int32_t n_steps,
             const int32_t* sliced_wires, int32_t k, const int32_t* open_qubits, int32_t n_open,
             const tn_plan_opts* opts, tn_plan_t* out);
 
-/* Contracts slices s_begin <= s < s_end and ACCUMULATES (+=) their sum into
+/* The sliced network is the sum of the networks with the sliced bonds fixed
+ * (main text, customized-TNC section), and slices are independent units of
+ * work (the outer level of the paper's two-level parallel scheme, main text).
+ * Contracts slices s_begin <= s < s_end and ACCUMULATES (+=) their sum into
  * amp (device memory, complex128[2^n_open]), in increasing slice order, on
  * `stream` (a hipStream_t; NULL = the null stream).  Asynchronous: returns
  * after enqueueing.  The per-slice result is widened to FP64 before it is
@@ -206,7 +210,11 @@ int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void
  * without an output shift (a permute) or an index out of range. */
 int tn_plan_shift_outputs(tn_plan_t p, int32_t op, int32_t delta);
 
-/* ---- batches of plans (many circuits in one launch) ---- */
+/* ---- batches of plans (many circuits in one launch) ----
+ * An extension with no counterpart in the paper: slices of several
+ * independent networks (different circuits) run as one captured launch.  Each
+ * network's value is still the sum over its slices (main text,
+ * customized-TNC section). */
 
 typedef struct tn_batch_s* tn_batch_t;
 
@@ -231,7 +239,10 @@ int tn_batch_destroy(tn_batch_t b);
  * stream, tn_batch_destroy. */
 int tn_contract_batch(const tn_plan_t* plans, const int64_t* ranges, void* const* amps, int32_t n, void* stream);
 
-/* Copies the plan's statistics into *s. */
+/* Copies the plan's statistics into *s: the per-slice contraction cost of
+ * the order (the complexity measure of Table I and of the Supplement's
+ * "Tensor network contraction algorithm" section, counted as 8 flops per
+ * complex multiply-add), the bytes of its tensors, and the slice count 2^k. */
 int tn_plan_info(tn_plan_t p, tn_plan_stats* s);
 
 /* Writes the plan as JSON (host folds, device leaves, per-step kernels with
@@ -245,11 +256,17 @@ int tn_plan_json(tn_plan_t p, char* buf, int64_t cap, int64_t* needed);
  * into out (host memory, 2 * 2^rank doubles).  For tests of the planner. */
 int tn_plan_leaf(tn_plan_t p, int32_t i, double* out, int64_t cap_doubles);
 
-/* Sticky numeric flags (TN_FLAG_*) of the plan's runs so far.  Synchronizes
+/* Numeric state of the mixed-precision mode that the main text names (the
+ * range checks are this library's scheme, see tn_plan_opts_default).
+ * Sticky numeric flags (TN_FLAG_*) of the plan's runs so far.  Synchronizes
  * the stream of the plan's last tn_contract_slices call. */
 int tn_plan_status(tn_plan_t p, uint32_t* flags);
 
-/* Rebinds the closed-qubit output bits without re-planning (re-folds and
+/* The target basis state enters the network only through the rank-1 output
+ * vectors of the closed qubits (main text, customized-TNC section: the
+ * network with a given target basis yields that basis's amplitude), so the
+ * same plan serves every bit string.
+ * Rebinds the closed-qubit output bits without re-planning (re-folds and
  * re-uploads the affected leaves).  Synchronous. */
 int tn_plan_set_output_bits(tn_plan_t p, const uint8_t* out_bits);
 

@@ -254,6 +254,9 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
     case kOpSkinny:
       HIP_TRY(launch_skinny(dt, a, b, c, op.idx, slot, s), "skewed contraction kernel");
       break;
+    case kOpSkew:
+      HIP_TRY(launch_skew(dt, a, b, c, op.idx, slot, s), "skewed matrix-core contraction kernel");
+      break;
     default:
       HIP_TRY(launch_generic(dt, a, b, c, op.idx, slot, s), "contraction kernel");
       break;
@@ -358,10 +361,11 @@ static int tune_plan(tn_plan_s* p) {
 // Kernel-class autotuning (the permute/GEMM fusion choice).  A step whose
 // shape admits more than one kernel class is run in each candidate class on
 // a one-step plan with the same operand layouts over buffers of its own
-// filled with random values; the fastest class overrides the planner's rule.  Candidates: the
-// gathered kernel against permutes + GEMM when the contraction is short
-// (2^nK <= 2^kFuseMaxK terms), and gathered, split-K and skewed against each
-// other for steps too narrow for the GEMM.  Steps whose buffers would exceed
+// filled with random values; the fastest class overrides the planner's rule.
+// Candidates: the gathered kernel (and the matrix-core skewed kernel where
+// valid) against permutes + GEMM when the contraction is short (2^nK <=
+// 2^kFuseMaxK terms), and gathered, split-K and the two skewed kernels
+// against each other for steps too narrow for the GEMM.  Steps whose buffers would exceed
 // the tuning budget (a third of the free device memory, at most
 // kClassTuneMaxBytes) keep the rule.  Choices are cached per process and in
 // the tuning database by dtype and the step's relabelled layouts.
@@ -464,8 +468,9 @@ static int tune_classes(PlanCore& P, bool measure) {
     if (valid & (1u << kOpGemm)) {
       if (st.nK > kFuseMaxK) continue;
       cand = {kOpGemm, kOpGeneric};
+      if (valid & (1u << kOpSkew)) cand.push_back(kOpSkew);
     } else {
-      for (int k : {kOpGeneric, kOpSplitK, kOpSkinny})
+      for (int k : {kOpGeneric, kOpSplitK, kOpSkinny, kOpSkew})
         if (valid & (1u << k)) cand.push_back(k);
       if (cand.size() < 2) continue;
     }

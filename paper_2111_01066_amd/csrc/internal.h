@@ -40,7 +40,7 @@ struct TRef {
   int64_t off = 0;  // element offset (complex elements) within the region
 };
 
-enum OpKind : int32_t { kOpPermute = 0, kOpGemm = 1, kOpGeneric = 2, kOpSkinny = 3, kOpSplitK = 4 };
+enum OpKind : int32_t { kOpPermute = 0, kOpGemm = 1, kOpGeneric = 2, kOpSkinny = 3, kOpSplitK = 4, kOpSkew = 5 };
 
 // Permute: output position q takes input position perm[q].
 struct PermuteOp {
@@ -186,21 +186,28 @@ void make_json(PlanCore& P);
 // Kernel classes of a step with 2^nM x 2^nN outputs over 2^nK terms.  dense
 // (permutes + MFMA GEMM): both free extents at least 64 (the smallest GEMM
 // tile) and K at least 16; split-K: at most 64 outputs; skewed (Supplement,
-// CPU-architecture section): the small operand fits in LDS, few outputs per
-// row of the large one; gathered: always valid.  Bit mask over OpKind.
+// CPU-architecture section): few outputs per row of the large operand, in
+// two kernels: on the vector units with the small operand in LDS (at most
+// 16 outputs per row, 2^(nK+nN) <= 2^kSkinnyMaxLog2 entries), and on the
+// matrix cores (at most 64 outputs per row, 2 <= K <= 2^10, at least 128
+// rows); gathered: always valid.  Bit mask over OpKind.
 inline unsigned step_classes(int nM, int nN, int nK) {
   unsigned m = 1u << kOpGeneric;
   if (nM >= 6 && nN >= 6 && nK >= 4) m |= 1u << kOpGemm;
   if (nM + nN <= 6 && nK >= 4) m |= 1u << kOpSplitK;
   if (nN <= 4 && nK + nN <= kSkinnyMaxLog2 && nM >= 8) m |= 1u << kOpSkinny;
+  if (nN <= 6 && nK >= 1 && nK <= 10 && nM >= 7) m |= 1u << kOpSkew;
   return m;
 }
-// The planner's rule among them: dense where valid, split-K for long sums
-// into few outputs, then skewed, then gathered.
+// The planner's rule among them: dense where valid and the contraction is
+// long (K >= 128) or the output wide (N >= 128), split-K for long sums into
+// few outputs, then the matrix-core skewed kernel, then the vector one, then
+// gathered.
 inline int default_class(int nM, int nN, int nK) {
   const unsigned m = step_classes(nM, nN, nK);
-  if (m & (1u << kOpGemm)) return kOpGemm;
+  if ((m & (1u << kOpGemm)) && (nK >= 7 || nN >= 7 || !(m & (1u << kOpSkew)))) return kOpGemm;
   if ((m & (1u << kOpSplitK)) && nK >= 10) return kOpSplitK;
+  if (m & (1u << kOpSkew)) return kOpSkew;
   if (m & (1u << kOpSkinny)) return kOpSkinny;
   return kOpGeneric;
 }

@@ -45,6 +45,10 @@ hipError_t launch_generic(int dtype, const void* A, const void* B, void* C, cons
 // skewed contraction with B and A's K offsets in LDS (nN <= 4, nK + nN <= kSkinnyMaxLog2)
 hipError_t launch_skinny(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
                          hipStream_t s);
+// skewed contraction on FP32 matrix cores (nN <= 6, 1 <= nK <= 10, nM >= 7)
+hipError_t launch_skew(int dtype, const void* A, const void* B, void* C, const IndexOp& op, float* maxslot,
+                       hipStream_t s);
+bool skew_ok(const IndexOp& op);
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s);
 int64_t splitk_blocks(const IndexOp& op);

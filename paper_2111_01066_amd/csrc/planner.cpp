@@ -801,7 +801,7 @@ int build_plan(PlanCore& P, std::string& err) {
       g.ssa_c = L + t;
       if (half) g.max_slot = P.n_slots++;
       P.ops.push_back(g);
-      if (skinny)
+      if (skinny || cls == kOpSkew)
         P.stats.n_skinny++;
       else
         P.stats.n_generic++;

@@ -191,18 +191,10 @@ def test_tuned_plan_vs_oracle_and_cache(tmp_path, dtype):
 
 def _candidates(st):
     """Kernel classes the class tuner times for a step (1 GEMM, 2 gathered,
-    3 skewed, 4 split-K): the gathered kernel against permutes + GEMM for
-    contractions of at most 2^6 terms, and every valid narrow class against
-    the others."""
-    nM, nN, nK = st["nM"], st["nN"], st["nK"]
-    if nM >= 6 and nN >= 6 and nK >= 4:
-        return [1, 2] if nK <= 6 else []
-    c = [2]
-    if nM + nN <= 6 and nK >= 4:
-        c.append(4)
-    if nN <= 4 and nK + nN <= 11 and nM >= 8:
-        c.append(3)
-    return c if len(c) > 1 else []
+    3 skewed on the vector units, 4 split-K, 5 skewed on the matrix cores):
+    the written rule of the planner's tests."""
+    from tests.test_planner_dryrun import _class_candidates
+    return _class_candidates(st)
 
 
 @pytest.mark.parametrize("dtype", ["c64", "f16s"])

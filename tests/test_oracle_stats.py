@@ -112,3 +112,22 @@ def test_xeb_ideal_and_uniform(deep20):
     f_uni = oracle.xeb_fidelity(p[uni], c.n_qubits)
     se_u = oracle.stats.xeb_stderr(p[uni], c.n_qubits)
     assert abs(f_uni) < 4 * se_u
+
+
+def test_xeb_stderr_porter_thomas_closed_forms():
+    """The standard error of the XEB estimate against closed forms: with
+    x = N p, uniform samples of a Porter-Thomas distribution have x ~ Exp(1)
+    (variance 1, s.e. 1/sqrt(n)), ideal samples have density x e^-x
+    (Gamma(2, 1): variance 2, s.e. sqrt(2/n)); and the estimate itself has
+    means 0 and 1 (Eq. (fxeb) with F = 0 and F = 1)."""
+    rng = np.random.default_rng(12)
+    n, nq = 400_000, 30
+    N = 2.0 ** nq
+    x_uni = rng.exponential(1.0, n)
+    x_ideal = rng.gamma(2.0, 1.0, n)
+    se_u = oracle.stats.xeb_stderr(x_uni / N, nq)
+    se_i = oracle.stats.xeb_stderr(x_ideal / N, nq)
+    assert se_u == pytest.approx(1.0 / np.sqrt(n), rel=0.01)
+    assert se_i == pytest.approx(np.sqrt(2.0 / n), rel=0.01)
+    assert abs(oracle.stats.xeb_fidelity(x_uni / N, nq)) < 4 * se_u
+    assert abs(oracle.stats.xeb_fidelity(x_ideal / N, nq) - 1.0) < 4 * se_i

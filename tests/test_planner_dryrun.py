@@ -191,26 +191,38 @@ def test_shift_outputs_on_dry_run_plan():
             plan.shift_outputs(1, op=perm[0])
 
 
+def _valid(nM, nN, nK):
+    v = {2}
+    if nM >= 6 and nN >= 6 and nK >= 4:
+        v.add(1)
+    if nM + nN <= 6 and nK >= 4:
+        v.add(4)
+    if nN <= 4 and nK + nN <= 11 and nM >= 8:
+        v.add(3)
+    if nN <= 6 and 1 <= nK <= 10 and nM >= 7:
+        v.add(5)
+    return v
+
+
 def _class_candidates(st):
     nM, nN, nK = st["nM"], st["nN"], st["nK"]
-    if nM >= 6 and nN >= 6 and nK >= 4:
-        return [1, 2] if nK <= 6 else []
-    c = [2]
-    if nM + nN <= 6 and nK >= 4:
-        c.append(4)
-    if nN <= 4 and nK + nN <= 11 and nM >= 8:
-        c.append(3)
+    v = _valid(nM, nN, nK)
+    if 1 in v:
+        return sorted({1, 2} | (v & {5})) if nK <= 6 else []
+    c = sorted(v & {2, 3, 4, 5})
     return c if len(c) > 1 else []
 
 
 def _default_class(st):
     nM, nN, nK = st["nM"], st["nN"], st["nK"]
-    if nM >= 6 and nN >= 6 and nK >= 4:
+    v = _valid(nM, nN, nK)
+    if 1 in v and (nK >= 7 or nN >= 7 or 5 not in v):
         return 1
-    if nM + nN <= 6 and nK >= 10:
+    if 4 in v and nK >= 10:
         return 4
-    if nN <= 4 and nK + nN <= 11 and nM >= 8:
-        return 3
+    for k in (5, 3):
+        if k in v:
+            return k
     return 2
 
 
