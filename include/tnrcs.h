@@ -143,8 +143,9 @@ typedef struct {
  * 2^6 terms; gathered, the two skewed kernels and split-K against each
  * other for steps with too few outputs for the GEMM)
  * is run in each on a one-step plan of the same operand layouts over
- * scratch buffers of random values (at most 8 GiB and a third of the free
- * device memory; larger steps keep the default rule), and the fastest is
+ * scratch buffers of random values (at most 48 GiB and a third of the free
+ * device memory; larger steps keep the default rule; the gathered kernel is
+ * timed only on steps of at most 2^22 outputs), and the fastest is
  * planned.  With the environment variable TNRCS_VERBOSE set, each tuned step
  * prints a line on stderr.  Tile:
  * for each distinct dense-GEMM shape of the plan (dtype, M, N, K, form)

@@ -370,7 +370,8 @@ static int tune_plan(tn_plan_s* p) {
 // kClassTuneMaxBytes) keep the rule.  Choices are cached per process and in
 // the tuning database by dtype and the step's relabelled layouts.
 constexpr int kFuseMaxK = 6;
-constexpr int64_t kClassTuneMaxBytes = (int64_t)8 << 30;
+constexpr int64_t kClassTuneMaxBytes = (int64_t)48 << 30;
+constexpr int kGatherTuneLog2 = 22;
 
 // Average time of one run of a one-step plan's ops in class `cls` (INFINITY
 // when the step does not fit the budget); builds, runs and frees the plan.
@@ -465,15 +466,21 @@ static int tune_classes(PlanCore& P, bool measure) {
   for (const PlanCore::StepInfo& st : P.steps) {
     const unsigned valid = step_classes(st.nM, st.nN, st.nK);
     std::vector<int> cand;
+    // the gathered kernel (one output per thread, operands re-read per
+    // output) is a candidate only for steps of at most 2^kGatherTuneLog2
+    // outputs: on larger ones it loses to every other class by far, and
+    // timing it would dominate the tuning time
+    const bool big = st.nM + st.nN > kGatherTuneLog2;
     if (valid & (1u << kOpGemm)) {
       if (st.nK > kFuseMaxK) continue;
-      cand = {kOpGemm, kOpGeneric};
+      cand = {kOpGemm};
+      if (!big) cand.push_back(kOpGeneric);
       if (valid & (1u << kOpSkew)) cand.push_back(kOpSkew);
     } else {
       for (int k : {kOpGeneric, kOpSplitK, kOpSkinny, kOpSkew})
-        if (valid & (1u << k)) cand.push_back(k);
-      if (cand.size() < 2) continue;
+        if ((valid & (1u << k)) && !(k == kOpGeneric && big && valid != (1u << kOpGeneric))) cand.push_back(k);
     }
+    if (cand.size() < 2) continue;
     const std::string& key = st.key;
     int best = -1;
     if (!class_lookup(P.opts.dtype, key, P.opts.tune_db, &best)) {

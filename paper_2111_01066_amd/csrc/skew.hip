@@ -4,21 +4,27 @@
 // written once).
 //
 // C[(m << nN) | n] = sum_k A[dep(m, aM) | dep(k, aK)] * B[dep(n, bN) | dep(k, bK)]
-// for N = 2^nN <= 64 outputs per row and any K = 2^nK >= 2, M = 2^nM >= 128
-// rows.  The operands are read in their stored layouts through bit-deposit
-// maps, so no permute runs before or after.  A workgroup of four waves takes
-// 128 consecutive rows per pass (32 per wave); the pass's A rows are gathered
-// chunk by chunk (16 k at a time) into LDS as planar FP32 re / im planes and
-// multiplied on v_mfma_f32_32x32x2_f32 against B, which is kept in LDS for
-// the whole kernel when it fits (else staged chunk by chunk with A).  Each
-// wave's 32 x 32 output tiles (one or two for N <= 32 / 64; columns n >= N
-// multiply zero rows of B and are not stored) go straight from the
-// accumulators to C, whose rows of a pass are one contiguous range.  3M
-// form on the matrix cores: T1 = ArBr, T2 = AiBi, T3 = (Ar+Ai)(Br+Bi).  Scaled
-// half storage is widened to FP32 when staged and rounded once on store.
+// for N = 2^nN <= 64 outputs per row and K = 2^nK >= 2, M = 2^nM >= 128 rows.
+// The operands are read in their stored layouts, so no permute runs before
+// or after.  A workgroup of four waves takes 128 consecutive rows per pass
+// (32 per wave) and walks K in chunks of up to 16.  A chunk's 128 x 16 A
+// entries sit at 2^11 addresses spanned by 11 bits of A's index; the
+// workgroup reads them in address order (consecutive threads, consecutive
+// addresses; 16-byte loads when A's lowest bits belong to the chunk), so a
+// chunk is a few long contiguous runs whatever the interleaving of M and K
+// bits in A's layout.  The chunk goes to LDS as planar FP32 re / im planes
+// and is multiplied on v_mfma_f32_32x32x2_f32 against B, kept in LDS for the
+// whole kernel when it fits (else staged per chunk); the next chunk's loads
+// are issued before the current chunk's products, so loads and matrix work
+// overlap.  Each wave's 32 x 32 output tiles (one or two for N <= 32 / 64;
+// columns n >= N multiply zero rows of B and are not stored) go straight from
+// the accumulators to C, whose rows of a pass are one contiguous range.  3M
+// form: T1 = ArBr, T2 = AiBi, T3 = (Ar+Ai)(Br+Bi).  Scaled half storage is
+// widened to FP32 when staged and rounded once on store.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "elem.h"
 #include "kernels.h"
@@ -26,42 +32,108 @@
 namespace tnrcs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int skew_u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSkewPM = 128;  // rows per pass
-constexpr int kSkewKC = 16;   // K staged per chunk
-constexpr int kSkewLDA = kSkewPM + 4;
+constexpr int kSkewKC = 16;   // K staged per chunk (fewer when K is smaller)
+constexpr int kSkewLDA = 160;  // LDS k-row stride (floats): 128 rows + 32, so rows k and k+1 sit 32 banks apart
+constexpr int kSkewMaxV = 11;  // index bits of one chunk: 7 row bits + up to 4 k bits
+
+// Address order of one chunk: chunk element e (0 .. 2^v) has its bit i at
+// A position pos[i], and is row bit mb[i] (or -1) / k bit kb[i] (or -1) of
+// the chunk; the bits are sorted by A position.  Row m, k of the chunk sits
+// in LDS at k * kSkewLDA + (m ^ h), h = XOR of hk[i] over the set k bits i
+// and of hm[j] over the set row bits 5 + j: a swizzle that keeps the 32 rows
+// a matrix-core operand reads at one k in 32 distinct banks, and gives the
+// 32 entries that one half-wave stores (consecutive in address order)
+// distinct banks too.
+struct SkewMap {
+  int32_t v;
+  int8_t pos[kSkewMaxV];
+  int8_t mb[kSkewMaxV];
+  int8_t kb[kSkewMaxV];
+  int8_t hk[4];
+  int8_t hm[2];
+};
 
 // LDS of one workgroup (bytes): A chunk planes, B planes (resident: all of
-// K; else one chunk), A's and B's K offset tables, the pass's row offsets.
+// K; else one chunk), B's K offset table, its N offsets, and A's offset of
+// every chunk's first k.
 static size_t skew_lds(int nK, int np, bool bres) {
   const size_t K = (size_t)1 << nK;
-  const size_t kb = bres ? K : (size_t)std::min<int64_t>(K, kSkewKC);
-  return 2 * kSkewKC * kSkewLDA * 4 + 2 * kb * (np + 4) * 4 + 2 * K * 8 + kSkewPM * 8 + 64 * 8;
+  const size_t kc = (size_t)std::min<int64_t>(K, kSkewKC);
+  const size_t kb = bres ? K : kc;
+  return 2 * kc * kSkewLDA * 4 + 2 * kb * (np + 4) * 4 + K * 8 + 64 * 8 + (K / kc) * 8;
 }
 
-// MFAST: consecutive threads gather consecutive rows m (A's lowest bits are
-// M bits); otherwise consecutive k (A's lowest bits are K bits).
-template <int NT, bool MFAST, typename E>
+__device__ __forceinline__ int skew_h(const SkewMap& mp, int m, int k) {
+  int h = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if ((k >> i) & 1) h ^= mp.hk[i];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    if ((m >> (5 + j)) & 1) h ^= mp.hm[j];
+  return h;
+}
+
+__device__ __forceinline__ void skew_split(const SkewMap& mp, int e, uint64_t& off, int& m, int& k) {
+  off = 0;
+  m = 0;
+  k = 0;
+  for (int i = 0; i < mp.v; ++i) {
+    const int b = (e >> i) & 1;
+    off |= (uint64_t)b << mp.pos[i];
+    if (mp.mb[i] >= 0) m |= b << mp.mb[i];
+    if (mp.kb[i] >= 0) k |= b << mp.kb[i];
+  }
+}
+
+// VEC consecutive chunk elements per load (VEC > 1: A's lowest log2(VEC)
+// index bits are the chunk's lowest bits, one 16-byte load).  LPT loads per
+// thread cover the 2^v chunk entries; DEPTH chunks are loaded ahead; KC k
+// per chunk (16, or K when K < 16).
+template <int NT, int VEC, int LPT, int DEPTH, int KC, typename E>
 __global__ __launch_bounds__(256, 2) void k_skew(const E* __restrict__ A, const E* __restrict__ B, E* __restrict__ C,
-                                             const IndexOp op, float* maxslot, int bres) {
+                                                const IndexOp op, const SkewMap mp, float* maxslot, int bres) {
   constexpr int NP = 32 * NT, LDB = NP + 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int K = 1 << op.nK, N = 1 << op.nN;
-  const int KC = K < kSkewKC ? K : kSkewKC;
   const int KB = bres ? K : KC;  // B rows held in LDS
-  float* As = reinterpret_cast<float*>(smem);            // [2][KC][LDA]
-  float* Bs = As + 2 * kSkewKC * kSkewLDA;               // [2][KB][LDB]
-  uint64_t* kA = reinterpret_cast<uint64_t*>(Bs + 2 * KB * LDB);  // [K]
-  uint64_t* kB = kA + K;                                 // [K]
-  uint64_t* am = kB + K;                                 // [PM]
-  uint64_t* bn = am + kSkewPM;                           // [64]
+  const int lnch = op.nK - __builtin_ctz(KC);  // log2 of the chunks per pass
+  float* As = reinterpret_cast<float*>(smem);                      // [2][KC][LDA]
+  float* Bs = As + 2 * KC * kSkewLDA;                              // [2][KB][LDB]
+  uint64_t* kB = reinterpret_cast<uint64_t*>(Bs + 2 * KB * LDB);  // [K]
+  uint64_t* bn = kB + K;                                           // [64]
+  uint64_t* kA0 = bn + 64;                                         // [K / KC]: A offset of chunk ch's k0
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 31, kh = lane >> 5;
-  for (int k = tid; k < K; k += 256) {
-    kA[k] = dep((uint64_t)k, op.aK);
-    kB[k] = dep((uint64_t)k, op.bK);
-  }
+  for (int k = tid; k < K; k += 256) kB[k] = dep((uint64_t)k, op.bK);
+  for (int ch = tid; ch < K / KC; ch += 256) kA0[ch] = dep((uint64_t)ch * KC, op.aK);
   if (tid < 64) bn[tid] = tid < N ? dep((uint64_t)tid, op.bN) : 0;
+  // this thread's chunk entries: load j covers elements (j * 256 + tid) * VEC + u
+  // (the launcher picks LPT * 256 * VEC = 2^v, so every thread has LPT full loads)
+  uint64_t eoff[LPT];
+  int eidx[LPT][VEC];  // LDS index of each entry
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      const int e = (j * 256 + tid) * VEC + u;
+      uint64_t off;
+      int m, k;
+      skew_split(mp, e, off, m, k);
+      if (u == 0) eoff[j] = off;
+      eidx[j][u] = k * kSkewLDA + (m ^ skew_h(mp, m, k));
+    }
+  }
+  // this lane's matrix-core operand entries: row 32 wave + c, k = kk + kh
+  int aidx[KC / 2];
+#pragma unroll
+  for (int s2 = 0; s2 < KC / 2; ++s2) {
+    const int k = 2 * s2 + kh, m = wave * 32 + c;
+    aidx[s2] = k * kSkewLDA + (m ^ skew_h(mp, m, k));
+  }
   __syncthreads();
   // B rows [k0, k0 + kn) into LDS rows [0, kn): Bs[p][k][n], zero for n >= N
   auto stage_b = [&](int k0, int kn) {
@@ -74,96 +146,413 @@ __global__ __launch_bounds__(256, 2) void k_skew(const E* __restrict__ A, const 
   };
   if (bres) stage_b(0, K);
   const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
-  float mx = 0.f;
-  for (int64_t ps = blockIdx.x; ps < passes; ps += gridDim.x) {
-    const int64_t m0 = ps * kSkewPM;
-    if (tid < kSkewPM) am[tid] = dep((uint64_t)(m0 + tid), op.aM);
-    floatx16 acc[3][NT];
+  const int64_t my_passes = passes > (int64_t)blockIdx.x ? (passes - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  const int64_t items = my_passes << lnch;
+  // A offset of a chunk: dep(m0, aM) | dep(k0, aK).  Both parts are
+  // advanced in the deposited domain instead of being recomputed (dep walks
+  // the run lists, which costs memory reads): the row part moves by
+  // dep(gridDim.x * PM) per pass through an add whose carries skip the bits
+  // that are not row bits (they are set to 1 first), the k part is tabulated
+  // per chunk.  One cursor for the chunk being prefetched.
+  const uint64_t mask_m = dep(((uint64_t)1 << op.nM) - kSkewPM, op.aM);  // row bits 7.. of A
+  const uint64_t inc_m = dep((uint64_t)gridDim.x * kSkewPM, op.aM);
+  uint64_t pf_m = dep((uint64_t)blockIdx.x * kSkewPM, op.aM);
+  int pf_ch = 0;
+  // DEPTH chunks in flight: chunk it lives in register set it % DEPTH from
+  // its loads until its LDS store, and set it % DEPTH is reloaded with chunk
+  // it + DEPTH right after that store
+  E v[DEPTH][LPT][VEC];
+  auto load_next = [&](E (&dst)[LPT][VEC]) {
+    const E* base = A + (pf_m | kA0[pf_ch]);
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int j = 0; j < NT; ++j) acc[p][j] = floatx16{};
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      __syncthreads();  // previous chunk consumed; am[] visible
-      // gather the chunk: PM x KC entries (KC even, so a multiple of 256),
-      // all of a thread's loads issued before its LDS stores
-      constexpr int EPT = kSkewPM * kSkewKC / 256;
-      const int n_el = kSkewPM * KC;
-      E v[EPT];
-      int mi[EPT], ki[EPT];
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = tid + q * 256;
-        if (MFAST) {
-          mi[q] = i % kSkewPM;
-          ki[q] = i / kSkewPM;
-        } else {
-          ki[q] = i % KC;
-          mi[q] = i / KC;
-        }
-        if (i < n_el) v[q] = A[am[mi[q]] | kA[k0 + ki[q]]];
-      }
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        if (tid + q * 256 < n_el) {
-          const float2 x = to_f2(v[q]);
-          As[ki[q] * kSkewLDA + mi[q]] = x.x;
-          As[(kSkewKC + ki[q]) * kSkewLDA + mi[q]] = x.y;
-        }
-      }
-      if (!bres) stage_b(k0, KC);
-      __syncthreads();
-      const int kb0 = bres ? k0 : 0;
-      for (int kk = 0; kk < KC; kk += 2) {
-        const int kr = kk + kh;
-        const float ar = As[kr * kSkewLDA + wave * 32 + c];
-        const float ai = As[(kSkewKC + kr) * kSkewLDA + wave * 32 + c];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const float br = Bs[(kb0 + kr) * LDB + 32 * j + c];
-          const float bi = Bs[(KB + kb0 + kr) * LDB + 32 * j + c];
-          acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc[0][j], 0, 0, 0);
-          acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc[1][j], 0, 0, 0);
-          acc[2][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, acc[2][j], 0, 0, 0);
-        }
+    for (int j = 0; j < LPT; ++j) {
+      if constexpr (VEC == 1) {
+        dst[j][0] = base[eoff[j]];
+      } else {
+        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        __builtin_memcpy(&dst[j][0], &w, 16);
       }
     }
-    // C rows m0 .. m0 + 127 are contiguous: row r of this wave's tile j,
-    // column c -> C[(m0 + 32 wave + row) * N + 32 j + c]
+    if (++pf_ch == (1 << lnch)) {
+      pf_ch = 0;
+      pf_m = ((pf_m | ~mask_m) + inc_m) & mask_m;
+    }
+  };
+  floatx16 acc[3][NT];
+  float mx = 0.f;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int col = 32 * j + c;
-      if (col < N) {
+  for (int d = 0; d < DEPTH; ++d)
+    if (d < items) load_next(v[d]);
+  for (int64_t it0 = 0; it0 < items; it0 += DEPTH) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-          const float cr = acc[0][j][r] - acc[1][j][r];
-          const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
-          mx = mag_max(mx, cr, ci);
-          C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+    for (int d = 0; d < DEPTH; ++d) {
+      const int64_t it = it0 + d;
+      if (it >= items) break;
+      const int ch = (int)(it & ((1 << lnch) - 1));
+      const int64_t m0 = ((int64_t)blockIdx.x + (it >> lnch) * (int64_t)gridDim.x) * kSkewPM;
+      __syncthreads();  // the previous chunk's products have read As (and Bs)
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) {
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+          const float2 x = to_f2(v[d][j][u]);
+          As[eidx[j][u]] = x.x;
+          As[KC * kSkewLDA + eidx[j][u]] = x.y;
+        }
+      }
+      if (it + DEPTH < items) load_next(v[d]);
+      if (!bres) stage_b(ch * KC, KC);
+      __syncthreads();
+      if (ch == 0) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+          for (int j = 0; j < NT; ++j) acc[p][j] = floatx16{};
+      }
+      const int kb0 = bres ? ch * KC : 0;
+      // the chunk's operands first (all LDS reads in flight together), then
+      // the products
+      float ar[KC / 2], ai[KC / 2], br[KC / 2][NT], bi[KC / 2][NT];
+#pragma unroll
+      for (int s2 = 0; s2 < KC / 2; ++s2) {
+        ar[s2] = As[aidx[s2]];
+        ai[s2] = As[KC * kSkewLDA + aidx[s2]];
+        const int kr = kb0 + 2 * s2 + kh;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          br[s2][j] = Bs[kr * LDB + 32 * j + c];
+          bi[s2][j] = Bs[(KB + kr) * LDB + 32 * j + c];
+        }
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < KC / 2; ++s2) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[s2], br[s2][j], acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[s2], bi[s2][j], acc[1][j], 0, 0, 0);
+          acc[2][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[s2] + ai[s2], br[s2][j] + bi[s2][j], acc[2][j], 0,
+                                                           0, 0);
+        }
+      }
+      if (ch == (1 << lnch) - 1) {
+        // C rows m0 .. m0 + 127 are contiguous: row r of this wave's tile j,
+        // column c -> C[(m0 + 32 wave + row) * N + 32 j + c]
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int col = 32 * j + c;
+          if (col < N) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+              const float cr = acc[0][j][r] - acc[1][j][r];
+              const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
+              mx = mag_max(mx, cr, ci);
+              C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+            }
+          }
         }
       }
     }
   }
-  record_max_in(maxslot, mx, reinterpret_cast<float*>(am));
+  __syncthreads();
+  record_max_in(maxslot, mx, reinterpret_cast<float*>(bn));
 }
+
+// Steady-state form for B resident in LDS and K = KC * NCH <= 64: one loop
+// iteration is one pass of 128 rows, its NCH chunks unrolled, so the loads,
+// LDS stores, matrix products and C stores of a pass are straight-line code
+// the compiler can schedule with exact memory counters.  Prefetch distance:
+// PD passes (the NCH * PD register slots hold the chunks of the next PD
+// passes; a chunk's slot is reloaded as soon as the chunk is in LDS, so
+// the loads spread over the pass); past the last pass the loads repeat the
+// last pass's chunks (read, never used).
+template <int NT, int VEC, int KC, int NCH, int PD, typename E>
+__global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, const E* __restrict__ B,
+                                                  E* __restrict__ C, const IndexOp op, const SkewMap mp,
+                                                  float* maxslot) {
+  constexpr int NP = 32 * NT, LDB = NP + 4, K = KC * NCH;
+  constexpr int LPT = (kSkewPM * KC) / 256 / VEC;  // loads per thread per chunk
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int N = 1 << op.nN;
+  float* As = reinterpret_cast<float*>(smem);  // [2][KC][LDA]
+  float* Bs = As + 2 * KC * kSkewLDA;          // [2][K][LDB]
+  uint64_t* bn = reinterpret_cast<uint64_t*>(Bs + 2 * K * LDB);  // [64]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 31, kh = lane >> 5;
+  if (tid < 64) bn[tid] = tid < N ? dep((uint64_t)tid, op.bN) : 0;
+  uint64_t kA0[NCH];  // A offset of each chunk's first k (uniform)
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) kA0[ch] = dep((uint64_t)ch * KC, op.aK);
+  uint64_t eoff[LPT];
+  int eidx[LPT][VEC];
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      uint64_t off;
+      int m, k;
+      skew_split(mp, (j * 256 + tid) * VEC + u, off, m, k);
+      if (u == 0) eoff[j] = off;
+      eidx[j][u] = k * kSkewLDA + (m ^ skew_h(mp, m, k));
+    }
+  }
+  int aidx[KC / 2];
+#pragma unroll
+  for (int s2 = 0; s2 < KC / 2; ++s2) {
+    const int k = 2 * s2 + kh, m = wave * 32 + c;
+    aidx[s2] = k * kSkewLDA + (m ^ skew_h(mp, m, k));
+  }
+  __syncthreads();
+  for (int i = tid; i < K * NP; i += 256) {
+    const int n = i % NP, k = i / NP;
+    const float2 v = n < N ? to_f2(B[bn[n] | dep((uint64_t)k, op.bK)]) : make_float2(0.f, 0.f);
+    Bs[k * LDB + n] = v.x;
+    Bs[(K + k) * LDB + n] = v.y;
+  }
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const int64_t my_passes = passes > (int64_t)blockIdx.x ? (passes - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  const uint64_t mask_m = dep(((uint64_t)1 << op.nM) - kSkewPM, op.aM);
+  const uint64_t inc_m = dep((uint64_t)gridDim.x * kSkewPM, op.aM);
+  uint64_t pf_m = dep((uint64_t)blockIdx.x * kSkewPM, op.aM);  // row part of the next pass to prefetch
+  int64_t pf_left = my_passes;                                   // passes not yet prefetched
+  E v[PD][NCH][LPT][VEC];
+  // chunk ch of the pass being prefetched into dst; after its last chunk the
+  // cursor moves to the next pass (the last pass is reloaded at the tail)
+  auto load_chunk = [&](E (&dst)[LPT][VEC], int ch) {
+    const E* base = A + (pf_m | kA0[ch]);
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      if constexpr (VEC == 1) {
+        dst[j][0] = base[eoff[j]];
+      } else {
+        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        __builtin_memcpy(&dst[j][0], &w, 16);
+      }
+    }
+    if (ch == NCH - 1) {
+      if (pf_left > 1) pf_m = ((pf_m | ~mask_m) + inc_m) & mask_m;
+      --pf_left;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) load_chunk(v[d][ch], ch);
+  float mx = 0.f;
+  for (int64_t p0 = 0; p0 < my_passes; p0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int64_t pi = p0 + d;
+      if (pi >= my_passes) break;
+      const int64_t m0 = ((int64_t)blockIdx.x + pi * (int64_t)gridDim.x) * kSkewPM;
+      floatx16 acc[3][NT];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[q][j] = floatx16{};
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        __syncthreads();  // the previous chunk's products have read As (B is staged before the first)
+#pragma unroll
+        for (int j = 0; j < LPT; ++j)
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            const float2 x = to_f2(v[d][ch][j][u]);
+            As[eidx[j][u]] = x.x;
+            As[KC * kSkewLDA + eidx[j][u]] = x.y;
+          }
+        // the slot is free: the same chunk PD passes ahead
+        load_chunk(v[d][ch], ch);
+        __syncthreads();
+        float ar[KC / 2], ai[KC / 2], br[KC / 2][NT], bi[KC / 2][NT];
+#pragma unroll
+        for (int s2 = 0; s2 < KC / 2; ++s2) {
+          ar[s2] = As[aidx[s2]];
+          ai[s2] = As[KC * kSkewLDA + aidx[s2]];
+          const int kr = ch * KC + 2 * s2 + kh;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            br[s2][j] = Bs[kr * LDB + 32 * j + c];
+            bi[s2][j] = Bs[(K + kr) * LDB + 32 * j + c];
+          }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < KC / 2; ++s2)
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[s2], br[s2][j], acc[0][j], 0, 0, 0);
+            acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[s2], bi[s2][j], acc[1][j], 0, 0, 0);
+            acc[2][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[s2] + ai[s2], br[s2][j] + bi[s2][j], acc[2][j],
+                                                             0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int col = 32 * j + c;
+        if (col < N) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            const float cr = acc[0][j][r] - acc[1][j][r];
+            const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
+            mx = mag_max(mx, cr, ci);
+            C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  record_max_in(maxslot, mx, reinterpret_cast<float*>(bn));
+}
+
+static size_t skew_p_lds(int kc, int K, int np) { return 2 * kc * kSkewLDA * 4 + 2 * K * (np + 4) * 4 + 64 * 8; }
 
 bool skew_ok(const IndexOp& op) { return op.nN <= 6 && op.nK >= 1 && op.nK <= 10 && op.nM >= 7; }
 
-template <int NT, typename E>
-static hipError_t launch_skew_t(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
-  const bool mfast = op.aM.n >= 1 && op.aM.src[0] == 0 && op.aM.dst[0] == 0;
+// Position in the target of bit j of a value deposited by runs r (-1: none).
+static int run_pos(const Runs& r, int j) {
+  for (int i = 0; i < r.n; ++i)
+    if (j >= r.src[i] && j < r.src[i] + r.len[i]) return r.dst[i] + (j - r.src[i]);
+  return -1;
+}
+
+static bool skew_map(const IndexOp& op, int kcb, int lv, SkewMap* mp) {
+  struct Var {
+    int pos, m, k;
+  };
+  std::vector<Var> vars;
+  for (int j = 0; j < 7; ++j) vars.push_back({run_pos(op.aM, j), j, -1});
+  for (int j = 0; j < kcb; ++j) vars.push_back({run_pos(op.aK, j), -1, j});
+  for (const Var& x : vars)
+    if (x.pos < 0) return false;
+  std::sort(vars.begin(), vars.end(), [](const Var& a, const Var& b) { return a.pos < b.pos; });
+  mp->v = (int)vars.size();
+  for (int i = 0; i < mp->v; ++i) {
+    mp->pos[i] = (int8_t)vars[i].pos;
+    mp->mb[i] = (int8_t)vars[i].m;
+    mp->kb[i] = (int8_t)vars[i].k;
+  }
+  // swizzle: a half-wave's store instruction covers chunk bits lv .. lv+4;
+  // row bits 0..4 among them are bank bits already, the others (k bits, row
+  // bits 5 and 6) are sent to the bank bits left free
+  for (int i = 0; i < 4; ++i) mp->hk[i] = 0;
+  mp->hm[0] = mp->hm[1] = 0;
+  unsigned used = 0;
+  for (int i = lv; i < std::min(mp->v, lv + 5); ++i)
+    if (mp->mb[i] >= 0 && mp->mb[i] < 5) used |= 1u << mp->mb[i];
+  int next = 0;
+  for (int i = lv; i < std::min(mp->v, lv + 5); ++i) {
+    const bool direct = mp->mb[i] >= 0 && mp->mb[i] < 5;
+    if (direct) continue;
+    while (next < 5 && (used >> next & 1)) ++next;
+    if (next >= 5) break;
+    used |= 1u << next;
+    if (mp->kb[i] >= 0)
+      mp->hk[mp->kb[i]] = (int8_t)(1 << next);
+    else
+      mp->hm[mp->mb[i] - 5] = (int8_t)(1 << next);
+  }
+  return true;
+}
+
+template <int NT, int VEC, int KC, typename E>
+static hipError_t launch_skew_v(const E* A, const E* B, E* C, const IndexOp& op, const SkewMap& mp, float* maxslot,
+                                hipStream_t s) {
   const int np = 32 * NT;
   const bool bres = skew_lds(op.nK, np, true) <= 64 * 1024;
   const size_t lds = skew_lds(op.nK, np, bres);
   if (lds > 64 * 1024) return hipErrorInvalidValue;
   const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
   const dim3 g((unsigned)std::min<int64_t>(passes, 2048));
-  if (mfast)
-    hipLaunchKernelGGL((k_skew<NT, true, E>), g, dim3(256), lds, s, A, B, C, op, maxslot, bres ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_skew<NT, false, E>), g, dim3(256), lds, s, A, B, C, op, maxslot, bres ? 1 : 0);
+  // loads per thread: 2^v entries over 256 threads, VEC per load (v >= 8,
+  // and VEC > 1 only when 2^v >= 256 VEC)
+  const int lpt = ((1 << mp.v) / 256) / VEC;
+  if (lpt < 1 || lpt * 256 * VEC != (1 << mp.v)) return hipErrorInvalidValue;
+  const int bres_i = bres ? 1 : 0;
+  // chunks loaded ahead: about 128 bytes per thread in flight
+  switch (lpt) {
+    case 1:
+      hipLaunchKernelGGL((k_skew<NT, VEC, 1, 4, KC, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot, bres_i);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_skew<NT, VEC, 2, (VEC * sizeof(E) >= 8 ? 4 : 2), KC, E>), g, dim3(256), lds, s, A, B,
+                         C, op, mp, maxslot, bres_i);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_skew<NT, VEC, 4, 2, KC, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot, bres_i);
+      break;
+    default:
+      if constexpr (VEC == 1)  // 2^11 entries, one per load (with 16-byte loads at most 4 per thread)
+        hipLaunchKernelGGL((k_skew<NT, VEC, 8, 2, KC, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot, bres_i);
+      else
+        return hipErrorInvalidValue;
+      break;
+  }
   return hipGetLastError();
+}
+
+template <int NT, int VEC, typename E>
+static hipError_t launch_skew_kc(const E* A, const E* B, E* C, const IndexOp& op, const SkewMap& mp,
+                                 float* maxslot, hipStream_t s) {
+  switch (op.nK) {
+    case 1: return launch_skew_v<NT, VEC, 2, E>(A, B, C, op, mp, maxslot, s);
+    case 2: return launch_skew_v<NT, VEC, 4, E>(A, B, C, op, mp, maxslot, s);
+    case 3: return launch_skew_v<NT, VEC, 8, E>(A, B, C, op, mp, maxslot, s);
+    default: return launch_skew_v<NT, VEC, kSkewKC, E>(A, B, C, op, mp, maxslot, s);
+  }
+}
+
+template <int NT, int VEC, int KC, int NCH, typename E>
+static hipError_t launch_skew_pass(const E* A, const E* B, E* C, const IndexOp& op, const SkewMap& mp,
+                                   float* maxslot, hipStream_t s) {
+  constexpr int PD = NCH >= 4 ? 1 : 2;  // prefetch distance in passes: NCH * PD chunks
+  const size_t lds = skew_p_lds(KC, KC * NCH, 32 * NT);
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const dim3 g((unsigned)std::min<int64_t>(passes, 512));
+  hipLaunchKernelGGL((k_skew_p<NT, VEC, KC, NCH, PD, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot);
+  return hipGetLastError();
+}
+
+template <int NT, int VEC, typename E>
+static hipError_t launch_skew_pk(const E* A, const E* B, E* C, const IndexOp& op, const SkewMap& mp, float* maxslot,
+                                 hipStream_t s) {
+  switch (op.nK) {
+    case 1:
+      if constexpr (VEC == 1) return launch_skew_pass<NT, VEC, 2, 1, E>(A, B, C, op, mp, maxslot, s);
+      break;
+    case 2:
+      if constexpr (VEC <= 2) return launch_skew_pass<NT, VEC, 4, 1, E>(A, B, C, op, mp, maxslot, s);
+      break;
+    case 3: return launch_skew_pass<NT, VEC, 8, 1, E>(A, B, C, op, mp, maxslot, s);
+    case 4: return launch_skew_pass<NT, VEC, 16, 1, E>(A, B, C, op, mp, maxslot, s);
+    case 5: return launch_skew_pass<NT, VEC, 16, 2, E>(A, B, C, op, mp, maxslot, s);
+    case 6: return launch_skew_pass<NT, VEC, 16, 4, E>(A, B, C, op, mp, maxslot, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int NT, typename E>
+static hipError_t launch_skew_t(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  constexpr int VEC = 16 / (int)sizeof(E);
+  constexpr int LV = VEC == 4 ? 2 : 1;
+  const int kcb = std::min(op.nK, 4);
+  // 16-byte loads: the chunk's lowest bits are A's lowest bits, and every
+  // thread gets at least one full vector
+  SkewMap mp{};
+  if (!skew_map(op, kcb, LV, &mp)) return hipErrorInvalidValue;
+  bool vec = (1 << mp.v) >= 256 * VEC;
+  for (int i = 0; i < LV; ++i) vec = vec && mp.pos[i] == i;
+  // pass kernel: K <= 64 with B resident
+  const bool pass = op.nK <= 6 && skew_p_lds(1 << kcb, 1 << op.nK, 32 * NT) <= 64 * 1024;
+  if (vec) {
+    if (pass) return launch_skew_pk<NT, VEC, E>(A, B, C, op, mp, maxslot, s);
+    return launch_skew_kc<NT, VEC, E>(A, B, C, op, mp, maxslot, s);
+  }
+  if (!skew_map(op, kcb, 0, &mp)) return hipErrorInvalidValue;
+  if (pass) return launch_skew_pk<NT, 1, E>(A, B, C, op, mp, maxslot, s);
+  return launch_skew_kc<NT, 1, E>(A, B, C, op, mp, maxslot, s);
 }
 
 template <typename E>

@@ -207,10 +207,16 @@ def _valid(nM, nN, nK):
 def _class_candidates(st):
     nM, nN, nK = st["nM"], st["nN"], st["nK"]
     v = _valid(nM, nN, nK)
+    big = nM + nN > 22  # the gathered kernel is not timed on large steps
     if 1 in v:
-        return sorted({1, 2} | (v & {5})) if nK <= 6 else []
-    c = sorted(v & {2, 3, 4, 5})
-    return c if len(c) > 1 else []
+        if nK > 6:
+            return []
+        c = {1} | (v & {5}) | (set() if big else {2})
+    else:
+        c = v & {2, 3, 4, 5}
+        if big and c != {2}:
+            c.discard(2)
+    return sorted(c) if len(c) > 1 else []
 
 
 def _default_class(st):
