@@ -162,9 +162,14 @@ __device__ __forceinline__ int lds_pad(int e) {
 // Tile of 2^TB elements (up to 2^12 complex64 or 2^13 four-byte elements,
 // 32 KB either way), 256 threads, 2^TB / 256 elements per thread.  All of
 // a thread's loads are issued before any LDS store so they are in flight
-// together; the writes are streaming (non-temporal) stores.  The parts of
-// the offsets that depend only on the unrolled iteration are tabulated once
-// in LDS.
+// together, and the next tile's loads are issued before the current tile
+// is read back from LDS and written out, so they overlap; the writes are
+// streaming (non-temporal) stores.  The parts of the offsets that depend
+// only on the unrolled iteration are tabulated once in LDS; the tile-id
+// parts are updated by one XOR per tile, so the loop does no bit-deposit
+// walks.
+// Past the last tile the prefetch repeats the last tile (read and staged,
+// never written out).
 template <int TB, typename E>
 __global__ __launch_bounds__(kPermThreads) void k_permute(const E* __restrict__ in, E* __restrict__ out,
                                                          const PermArgs a) {
@@ -187,19 +192,57 @@ __global__ __launch_bounds__(kPermThreads) void k_permute(const E* __restrict__ 
   const uint64_t e_t = dep((uint64_t)tid * G, a.in_tile);
   const uint64_t f_t = dep((uint64_t)tid * G, a.out_tile);
   const int fe_t = (int)dep((uint64_t)tid * G, a.f2e);
+  // tile-id parts of the offsets.  Block b takes tiles t_i = b + i P (P =
+  // gridDim.x, a power of two like the tile count), so dep(t_i) = dep(b) XOR
+  // dep(i P), and from i to i + 1 the bits 0..ctz(i + 1) of i flip: the
+  // offsets move by one XOR with a prefix table of dep(2^j P) (the tile-id
+  // map need not preserve bit order, so no carrying add)
+  __shared__ uint64_t pre_in[40], pre_out[40];
+  const int lg = __builtin_ctzll((unsigned long long)gridDim.x);
+  const int nb = __builtin_ctzll((unsigned long long)a.n_tiles) - lg;  // bits of the iteration index
+  if (tid < nb) {
+    uint64_t xi = 0, xo = 0;
+    for (int j = 0; j <= tid; ++j) {
+      xi ^= dep((uint64_t)1 << (lg + j), a.id_in);
+      xo ^= dep((uint64_t)1 << (lg + j), a.id_out);
+    }
+    pre_in[tid] = xi;
+    pre_out[tid] = xo;
+  }
+  const uint64_t din = dep((uint64_t)blockIdx.x, a.id_in);
+  uint64_t dout = dep((uint64_t)blockIdx.x, a.id_out);
+  const int64_t my_tiles = a.n_tiles > (int64_t)blockIdx.x ? (a.n_tiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
   __syncthreads();
   int fl[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) fl[g] = fe_low[g];
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-    const uint64_t ib = dep((uint64_t)t, a.id_in) | e_t;
-    const uint64_t ob = dep((uint64_t)t, a.id_out) | f_t;
-    u32x4 v[PG];
+  uint64_t pf_in = din;  // input offset of the tile being prefetched
+  int64_t pf_i = 0;      // its iteration index
+  u32x4 v[PG];
+  auto load_tile = [&]() {
+    const uint64_t ib = pf_in | e_t;
 #pragma unroll
     for (int i = 0; i < PG; ++i) v[i] = *reinterpret_cast<const u32x4*>(src + (ib | hi_in[i]));
+    if (pf_i + 1 < my_tiles) {
+      ++pf_i;
+      pf_in ^= pre_in[__builtin_ctzll((unsigned long long)pf_i)];
+    }
+  };
+  auto stage = [&]() {
 #pragma unroll
     for (int i = 0; i < PG; ++i) *reinterpret_cast<u32x4*>(&tile[lds_pad<G>(G * (i * kPermThreads + tid))]) = v[i];
+  };
+  if (my_tiles > 0) {
+    load_tile();
+    stage();
     __syncthreads();
+    load_tile();
+  }
+  // per tile: write out the staged tile, then stage the prefetched one and
+  // prefetch the next: the wait for the prefetched loads comes after this
+  // tile's stores in every iteration, so the stores may still be in flight
+  for (int64_t i_t = 0; i_t < my_tiles; ++i_t) {
+    const uint64_t ob = dout | f_t;
 #pragma unroll
     for (int i = 0; i < PG; ++i) {
       const int e0 = fe_t | hi_fe[i];
@@ -210,7 +253,11 @@ __global__ __launch_bounds__(kPermThreads) void k_permute(const E* __restrict__ 
       __builtin_memcpy(&x, w, 16);
       __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dst + (ob | hi_out[i])));
     }
+    if (i_t + 1 < my_tiles) dout ^= pre_out[__builtin_ctzll((unsigned long long)(i_t + 1))];
     __syncthreads();
+    stage();
+    __syncthreads();
+    load_tile();
   }
 }
 
@@ -489,8 +536,17 @@ __global__ __launch_bounds__(256) void k_skinny(const E* __restrict__ A, const E
   __syncthreads();
   const int tid = threadIdx.x;
   const int64_t nm = (int64_t)1 << op.nM;  // a multiple of PM
+  // row offsets dep(m0 + r 256 + tid) = dep(m0) | dep(r 256 + tid): the
+  // first part advanced in the deposited domain per pass, the second fixed
+  uint64_t am_t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) am_t[r] = dep((uint64_t)(r * 256 + tid), op.aM);
+  const uint64_t mask_m = dep((uint64_t)(nm - PM), op.aM);
+  const uint64_t inc_m = dep((uint64_t)gridDim.x * PM, op.aM);
+  uint64_t am0 = dep((uint64_t)blockIdx.x * PM, op.aM);
   float mx = 0.f;
-  for (int64_t m0 = (int64_t)blockIdx.x * PM; m0 < nm; m0 += (int64_t)gridDim.x * PM) {
+  for (int64_t m0 = (int64_t)blockIdx.x * PM; m0 < nm;
+       m0 += (int64_t)gridDim.x * PM, am0 = ((am0 | ~mask_m) + inc_m) & mask_m) {
     float re[R][NN], im[R][NN];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -529,7 +585,7 @@ __global__ __launch_bounds__(256) void k_skinny(const E* __restrict__ A, const E
     } else {
       uint64_t am[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) am[r] = dep((uint64_t)(m0 + r * 256 + tid), op.aM);
+      for (int r = 0; r < R; ++r) am[r] = am0 | am_t[r];
       for (int k = 0; k < nk; ++k) {
         float2 x[R];
 #pragma unroll

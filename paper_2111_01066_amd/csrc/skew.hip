@@ -408,6 +408,165 @@ __global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, cons
 
 static size_t skew_p_lds(int kc, int K, int np) { return 2 * kc * kSkewLDA * 4 + 2 * K * (np + 4) * 4 + 64 * 8; }
 
+// Scaled FP16 / BF16 storage on the half-precision matrix cores
+// (v_mfma_f32_32x32x16_{f16,bf16}: 16 k per instruction, FP32 accumulation)
+// in the 4M form, Cr = Ar Br + (-Ai) Bi, Ci = Ar Bi + Ai Br: the products of
+// the stored 16-bit values are exact in the FP32 accumulator, so no operand
+// sum is rounded.  Same pass structure as k_skew_p with KC = 16; the chunk
+// goes to LDS as planar 16-bit rows [m][k] (k contiguous, rows padded to 24
+// entries) so that each lane reads its eight consecutive k in one 16-byte
+// load, and B is resident as planar rows [n][k].
+typedef _Float16 skew_half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 skew_bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kSkewHS = 24;  // LDS row stride of the 16-bit planes (entries)
+
+template <typename E>
+struct SkewHalf;
+template <>
+struct SkewHalf<cf16> {
+  typedef _Float16 H;
+  typedef skew_half8 V;
+  static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SkewHalf<cbf16> {
+  typedef __bf16 H;
+  typedef skew_bf16x8 V;
+  static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int NT, int VEC, int NCH, int PD, typename E>
+__global__ __launch_bounds__(256, 2) void k_skew_ph(const E* __restrict__ A, const E* __restrict__ B,
+                                                   E* __restrict__ C, const IndexOp op, const SkewMap mp,
+                                                   float* maxslot) {
+  typedef typename SkewHalf<E>::H H;
+  typedef typename SkewHalf<E>::V V;
+  constexpr int KC = 16, NP = 32 * NT, K = KC * NCH;
+  constexpr int LPT = (kSkewPM * KC) / 256 / VEC;
+  constexpr int KS = K + 8;  // B row stride (entries): 16-byte aligned rows
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int N = 1 << op.nN;
+  H* As = reinterpret_cast<H*>(smem);            // [2][PM][kSkewHS]
+  H* Bs = As + 2 * kSkewPM * kSkewHS;            // [2][NP][KS]
+  uint64_t* bn = reinterpret_cast<uint64_t*>(Bs + 2 * NP * KS);  // [64]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 31, kh = lane >> 5;
+  if (tid < 64) bn[tid] = tid < N ? dep((uint64_t)tid, op.bN) : 0;
+  uint64_t kA0[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) kA0[ch] = dep((uint64_t)ch * KC, op.aK);
+  uint64_t eoff[LPT];
+  int eidx[LPT][VEC];  // LDS index m * kSkewHS + k of each entry
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      uint64_t off;
+      int m, k;
+      skew_split(mp, (j * 256 + tid) * VEC + u, off, m, k);
+      if (u == 0) eoff[j] = off;
+      eidx[j][u] = m * kSkewHS + k;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < K * NP; i += 256) {
+    const int k = i % K, n = i / K;
+    E v{};
+    if (n < N) v = B[bn[n] | dep((uint64_t)k, op.bK)];
+    Bs[n * KS + k] = v.re;
+    Bs[(NP + n) * KS + k] = v.im;
+  }
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const int64_t my_passes = passes > (int64_t)blockIdx.x ? (passes - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  const uint64_t mask_m = dep(((uint64_t)1 << op.nM) - kSkewPM, op.aM);
+  const uint64_t inc_m = dep((uint64_t)gridDim.x * kSkewPM, op.aM);
+  uint64_t pf_m = dep((uint64_t)blockIdx.x * kSkewPM, op.aM);
+  int64_t pf_left = my_passes;
+  E v[PD][NCH][LPT][VEC];
+  auto load_chunk = [&](E (&dst)[LPT][VEC], int ch) {
+    const E* base = A + (pf_m | kA0[ch]);
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      if constexpr (VEC == 1) {
+        dst[j][0] = base[eoff[j]];
+      } else {
+        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        __builtin_memcpy(&dst[j][0], &w, 16);
+      }
+    }
+    if (ch == NCH - 1) {
+      if (pf_left > 1) pf_m = ((pf_m | ~mask_m) + inc_m) & mask_m;
+      --pf_left;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) load_chunk(v[d][ch], ch);
+  const int arow = (wave * 32 + c) * kSkewHS + 8 * kh;  // this lane's 8 k of its row
+  float mx = 0.f;
+  for (int64_t p0 = 0; p0 < my_passes; p0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int64_t pi = p0 + d;
+      if (pi >= my_passes) break;
+      const int64_t m0 = ((int64_t)blockIdx.x + pi * (int64_t)gridDim.x) * kSkewPM;
+      floatx16 acc[2][NT];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[q][j] = floatx16{};
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < LPT; ++j)
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            As[eidx[j][u]] = v[d][ch][j][u].re;
+            As[kSkewPM * kSkewHS + eidx[j][u]] = v[d][ch][j][u].im;
+          }
+        load_chunk(v[d][ch], ch);
+        __syncthreads();
+        const V ar = *reinterpret_cast<const V*>(As + arow);
+        const V ai = *reinterpret_cast<const V*>(As + kSkewPM * kSkewHS + arow);
+        const V nai = -ai;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int brow = (32 * j + c) * KS + ch * KC + 8 * kh;
+          const V br = *reinterpret_cast<const V*>(Bs + brow);
+          const V bi = *reinterpret_cast<const V*>(Bs + NP * KS + brow);
+          acc[0][j] = SkewHalf<E>::mfma(ar, br, acc[0][j]);
+          acc[0][j] = SkewHalf<E>::mfma(nai, bi, acc[0][j]);
+          acc[1][j] = SkewHalf<E>::mfma(ar, bi, acc[1][j]);
+          acc[1][j] = SkewHalf<E>::mfma(ai, br, acc[1][j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int col = 32 * j + c;
+        if (col < N) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            const float cr = acc[0][j][r], ci = acc[1][j][r];
+            mx = mag_max(mx, cr, ci);
+            C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  record_max_in(maxslot, mx, reinterpret_cast<float*>(bn));
+}
+
+static size_t skew_ph_lds(int K, int np) { return 2 * kSkewPM * kSkewHS * 2 + 2 * np * (K + 8) * 2 + 64 * 8; }
+
 bool skew_ok(const IndexOp& op) { return op.nN <= 6 && op.nK >= 1 && op.nK <= 10 && op.nM >= 7; }
 
 // Position in the target of bit j of a value deposited by runs r (-1: none).
@@ -555,8 +714,46 @@ static hipError_t launch_skew_t(const E* A, const E* B, E* C, const IndexOp& op,
   return launch_skew_kc<NT, 1, E>(A, B, C, op, mp, maxslot, s);
 }
 
+template <int NT, int VEC, int NCH, typename E>
+static hipError_t launch_skew_half(const E* A, const E* B, E* C, const IndexOp& op, const SkewMap& mp,
+                                   float* maxslot, hipStream_t s) {
+  constexpr int PD = NCH >= 4 ? 1 : 2;
+  const size_t lds = skew_ph_lds(16 * NCH, 32 * NT);
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const dim3 g((unsigned)std::min<int64_t>(passes, 512));
+  hipLaunchKernelGGL((k_skew_ph<NT, VEC, NCH, PD, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot);
+  return hipGetLastError();
+}
+
+// 16-bit storage with 16 <= K <= 64: the half-precision matrix cores
+template <int NT, typename E>
+static hipError_t launch_skew_h(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  constexpr int VEC = 16 / (int)sizeof(E);
+  SkewMap mp{};
+  if (!skew_map(op, 4, 2, &mp)) return hipErrorInvalidValue;
+  const bool vec = mp.pos[0] == 0 && mp.pos[1] == 1;
+  if (vec) {
+    switch (op.nK) {
+      case 4: return launch_skew_half<NT, VEC, 1, E>(A, B, C, op, mp, maxslot, s);
+      case 5: return launch_skew_half<NT, VEC, 2, E>(A, B, C, op, mp, maxslot, s);
+      default: return launch_skew_half<NT, VEC, 4, E>(A, B, C, op, mp, maxslot, s);
+    }
+  }
+  switch (op.nK) {
+    case 4: return launch_skew_half<NT, 1, 1, E>(A, B, C, op, mp, maxslot, s);
+    case 5: return launch_skew_half<NT, 1, 2, E>(A, B, C, op, mp, maxslot, s);
+    default: return launch_skew_half<NT, 1, 4, E>(A, B, C, op, mp, maxslot, s);
+  }
+}
+
 template <typename E>
 static hipError_t launch_skew_e(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  if constexpr (sizeof(E) == 4) {
+    if (op.nK >= 4 && op.nK <= 6) {
+      if (op.nN <= 5) return launch_skew_h<1, E>(A, B, C, op, maxslot, s);
+      return launch_skew_h<2, E>(A, B, C, op, maxslot, s);
+    }
+  }
   if (op.nN <= 5) return launch_skew_t<1, E>(A, B, C, op, maxslot, s);
   return launch_skew_t<2, E>(A, B, C, op, maxslot, s);
 }

@@ -49,6 +49,37 @@ def test_permute_bit_exact(rank):
         np.testing.assert_array_equal(out.cpu().numpy(), _np_permute(x, perm))
 
 
+def _gpu_source_index(rank, perm):
+    """Input index of every output index, computed on the device."""
+    o = torch.arange(1 << rank, dtype=torch.int64, device=DEV)
+    i = torch.zeros_like(o)
+    for q, p in enumerate(perm):
+        i |= ((o >> q) & 1) << p
+    return i
+
+
+@pytest.mark.parametrize("rank,elem_bytes", [(29, 8), (30, 4)])
+def test_permute_many_tiles_per_block(rank, elem_bytes):
+    """Tensors with more tiles than blocks (16384 blocks, tiles of 2^12 or
+    2^13 elements), so each block walks several tiles and advances its
+    tile-id offsets in the loop; every element is checked bit-exact (each
+    input element holds its own index)."""
+    rng = np.random.default_rng(7 * rank)
+    dt = torch.int64 if elem_bytes == 8 else torch.int32
+    x = torch.arange(1 << rank, dtype=dt, device=DEV)
+    out = torch.empty_like(x)
+    for trial, perm in enumerate([rng.permutation(rank).tolist(), list(range(rank))[::-1],
+                                  list(range(rank // 2, rank)) + list(range(rank // 2))]):
+        print(f"permute rank={rank} elem_bytes={elem_bytes} trial={trial}", flush=True)
+        out.fill_(-1)
+        tnrcs.tn_permute(x, out, perm, batch=1, elem_bytes=elem_bytes)
+        torch.cuda.synchronize()
+        want = _gpu_source_index(rank, perm).to(dt)
+        bad = int((out != want).sum())
+        assert bad == 0, f"{bad} wrong elements"
+        del want
+
+
 def test_permute_rejects_bad_perm():
     x = torch.zeros(8, dtype=torch.complex64, device=DEV)
     with pytest.raises(tnrcs.TnError):
