@@ -167,7 +167,7 @@ def slice_roofline_frac(res, dtype):
     return t / res["sec_per_slice"]
 
 
-def roofline(by_kind, dtype):
+def roofline(by_kind, dtype, copy_gbs=None):
     dom = max(by_kind, key=lambda k: by_kind[k]["ms"])
     d = by_kind[dom]
     avg_ms = d["ms"] / d["n"]
@@ -182,9 +182,37 @@ def roofline(by_kind, dtype):
                         "8 in 4M) / mean launch duration (HIP events on the launch stream); traffic = HBM bytes "
                         "per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain copy)"}
     achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype), "launches_per_slice": d["n"],
-            "avg_ms": avg_ms, "bytes_per_launch": d["bytes"] / d["n"]}
+    r = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+         "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype), "launches_per_slice": d["n"],
+         "avg_ms": avg_ms, "bytes_per_launch": d["bytes"] / d["n"],
+         "note": "achieved = algorithmic bytes per launch (each operand read once, the output written once) / "
+                 "mean launch duration (HIP events on the launch stream)"}
+    if copy_gbs:
+        r["copy_probe_GB/s"] = copy_gbs
+        r["frac_of_copy_probe"] = achieved / copy_gbs
+    return r
+
+
+def copy_ceiling(tnrcs, torch, gib: int = 8, reps: int = 5):
+    """The practical HBM ceiling of a kernel that reads and writes about as
+    much: the streaming copy probe on two gib-GiB buffers, median of reps
+    launches (HIP events on the current stream)."""
+    nb = gib << 30
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    tnrcs.tn_probe_copy(src, dst, nb)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tnrcs.tn_probe_copy(src, dst, nb)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nb / sorted(ts)[reps // 2] / 1e6
 
 
 def micro(tnrcs, torch, np):
@@ -550,7 +578,11 @@ def main():
     main_res = run_network(tnrcs, torch, w, args.dtype, args.form, K, W, graph=not args.no_graph,
                            tune=not args.no_tune, tune_db=args.tune_db)
     by_kind, split = kernel_split(main_res, args.dtype)
-    roof = roofline(by_kind, args.dtype)
+    cc = copy_ceiling(tnrcs, torch)
+    roof = roofline(by_kind, args.dtype, cc)
+    if roof["bound"] == "hbm":
+        log(f"[bench] {roof['kernel']}: {roof['achieved']:.0f} GB/s, {roof['frac']:.1%} of 8 TB/s, "
+            f"{roof['achieved'] / cc:.1%} of the streaming copy probe ({cc:.0f} GB/s)")
     info = main_res["info"]
     main_res["plan"].close()
     del main_res["plan"]
@@ -579,7 +611,7 @@ def main():
                         "rel_err_vs_" + args.dtype: err, "flags": r["flags"]}
             if "ops" in r:
                 bk, _ = kernel_split(r, dt)
-                prec[dt]["roofline"] = roofline(bk, dt)
+                prec[dt]["roofline"] = roofline(bk, dt, cc)
             log(f"[bench] {dt}: {main_res['sec_per_slice'] / r['sec_per_slice']:.2f}x faster than {args.dtype}, "
                 f"bunch relative error vs {args.dtype} over the {K} timed slices {err:.2e}")
             r["plan"].close()
@@ -622,6 +654,7 @@ def main():
             "time_to_amplitudes_s": sec * n_slices,
             "time_to_amplitudes_note": ("all slices of the bunch timed" if K == n_slices else
                                         f"{K} of {n_slices} slices timed, time per slice x slice count"),
+            "time_to_amplitudes_with_plan_s": main_res["plan_s"] + sec * n_slices,
             "flops_per_slice": info["flops_per_slice"],
             "bytes_per_slice": info["bytes_per_slice"],
             "gemm_form": args.form,

@@ -370,9 +370,11 @@ int tn_cgemm_c64_noalloc(const void* A, const void* B, void* C, int64_t M, int64
 int tn_probe_mfma(int32_t kind, int64_t iters, void* out_dev, double* flops, void* stream);
 int64_t tn_probe_mfma_out_floats(void);
 
-/* Streaming device copy (16-byte loads and nontemporal stores) of `bytes`
- * (a multiple of 16; both pointers 16-byte aligned, not overlapping), the
- * HBM ceiling of the data-movement kernels.  Asynchronous on `stream`. */
+/* Streaming device copy (16-byte nontemporal loads and stores, 16384
+ * blocks) of `bytes` (a multiple of 16; both pointers 16-byte aligned, not
+ * overlapping): the practical HBM ceiling of the data-movement kernels,
+ * which read and write about as much as a copy does.  Asynchronous on
+ * `stream`. */
 int tn_probe_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 /* FP64 reductions over an amplitude buffer (complex128, device):

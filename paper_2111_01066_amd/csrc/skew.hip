@@ -33,6 +33,33 @@ namespace tnrcs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef unsigned int skew_u32x4 __attribute__((ext_vector_type(4)));
+// A is read once and C written once per launch, both far larger than the
+// caches: nontemporal loads and stores (about 3 % faster on the 2^32-entry
+// steps of the 53-qubit network)
+template <typename E>
+__device__ __forceinline__ E skew_ld_nt(const E* p) {
+  E e;
+  if constexpr (sizeof(E) == 8) {
+    const unsigned long long w = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+    __builtin_memcpy(&e, &w, 8);
+  } else {
+    const unsigned w = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
+    __builtin_memcpy(&e, &w, 4);
+  }
+  return e;
+}
+template <typename E>
+__device__ __forceinline__ void skew_st_nt(E* p, E e) {
+  if constexpr (sizeof(E) == 8) {
+    unsigned long long w;
+    __builtin_memcpy(&w, &e, 8);
+    __builtin_nontemporal_store(w, reinterpret_cast<unsigned long long*>(p));
+  } else {
+    unsigned w;
+    __builtin_memcpy(&w, &e, 4);
+    __builtin_nontemporal_store(w, reinterpret_cast<unsigned*>(p));
+  }
+}
 
 constexpr int kSkewPM = 128;  // rows per pass
 constexpr int kSkewKC = 16;   // K staged per chunk (fewer when K is smaller)
@@ -167,9 +194,9 @@ __global__ __launch_bounds__(256, 2) void k_skew(const E* __restrict__ A, const 
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       if constexpr (VEC == 1) {
-        dst[j][0] = base[eoff[j]];
+        dst[j][0] = skew_ld_nt(base + eoff[j]);
       } else {
-        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        const skew_u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const skew_u32x4*>(base + eoff[j]));
         __builtin_memcpy(&dst[j][0], &w, 16);
       }
     }
@@ -247,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void k_skew(const E* __restrict__ A, const 
               const float cr = acc[0][j][r] - acc[1][j][r];
               const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
               mx = mag_max(mx, cr, ci);
-              C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+              skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
             }
           }
         }
@@ -323,9 +350,9 @@ __global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, cons
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       if constexpr (VEC == 1) {
-        dst[j][0] = base[eoff[j]];
+        dst[j][0] = skew_ld_nt(base + eoff[j]);
       } else {
-        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        const skew_u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const skew_u32x4*>(base + eoff[j]));
         __builtin_memcpy(&dst[j][0], &w, 16);
       }
     }
@@ -396,7 +423,7 @@ __global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, cons
             const float cr = acc[0][j][r] - acc[1][j][r];
             const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
             mx = mag_max(mx, cr, ci);
-            C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+            skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
           }
         }
       }
@@ -492,9 +519,9 @@ __global__ __launch_bounds__(256, 2) void k_skew_ph(const E* __restrict__ A, con
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
       if constexpr (VEC == 1) {
-        dst[j][0] = base[eoff[j]];
+        dst[j][0] = skew_ld_nt(base + eoff[j]);
       } else {
-        const skew_u32x4 w = *reinterpret_cast<const skew_u32x4*>(base + eoff[j]);
+        const skew_u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const skew_u32x4*>(base + eoff[j]));
         __builtin_memcpy(&dst[j][0], &w, 16);
       }
     }
@@ -555,7 +582,7 @@ __global__ __launch_bounds__(256, 2) void k_skew_ph(const E* __restrict__ A, con
             const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
             const float cr = acc[0][j][r], ci = acc[1][j][r];
             mx = mag_max(mx, cr, ci);
-            C[((m0 + row) << op.nN) | col] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+            skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
           }
         }
       }
