@@ -238,7 +238,10 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
       HIP_TRY(launch_permute(p->eb, a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
       break;
     case kOpGemm:
-      if (dt == TN_DTYPE_C64)
+      if (op.gemm.gather_a)
+        HIP_TRY(launch_gemm_c64_ga((const float2*)a, (const float2*)b, (float2*)c, op.idx, op.gemm.form, s),
+                "gemm kernel (A in place)");
+      else if (dt == TN_DTYPE_C64)
         HIP_TRY(launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, op.gemm.M, op.gemm.N, op.gemm.K, 1,
                                 op.gemm.form, s, op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.tile),
                 "gemm kernel");
@@ -342,7 +345,7 @@ static int tune_plan(tn_plan_s* p) {
     HIP_TRY(launch_fill_random(p->d_arena, P.arena_elems * p->eb, P.opts.dtype, nullptr), "fill arena");
   HIP_TRY(hipDeviceSynchronize(), "tuner synchronize");
   for (Op& op : P.ops) {
-    if (op.kind != kOpGemm) continue;
+    if (op.kind != kOpGemm || op.gemm.gather_a) continue;
     std::string err;
     float* slot = op.max_slot >= 0 ? p->d_maxslots + op.max_slot : nullptr;
     float2* w = op.gemm.split_max > 1 ? reinterpret_cast<float2*>(resolve(p, op.w)) : nullptr;
@@ -426,7 +429,7 @@ static int time_class(const PlanCore& P, const std::vector<int>& a, const std::v
   q.ext_c = C;
   // the GEMM of the dense class runs its own tuned variant
   for (Op& op : Q.ops)
-    if (op.kind == kOpGemm && (rc = tune_gemm(Q.opts.dtype, op.gemm, resolve(&q, op.a), resolve(&q, op.b),
+    if (op.kind == kOpGemm && !op.gemm.gather_a && (rc = tune_gemm(Q.opts.dtype, op.gemm, resolve(&q, op.a), resolve(&q, op.b),
                                                 resolve(&q, op.c),
                                                 op.gemm.split_max > 1 ? (float2*)resolve(&q, op.w) : nullptr,
                                                 op.max_slot >= 0 ? q.d_maxslots + op.max_slot : nullptr,

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "elem.h"
+#include "gather.h"
 #include "kernels.h"
 
 namespace tnrcs {
@@ -124,20 +125,35 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
     flush(std::true_type{});
 }
 
+// A read in place (GA = 1): the large operand's rows and contracted bits
+// sit anywhere in its stored layout (row bit i at the position of aM bit i,
+// k bit i at that of aK bit i, the k bits above 3 in increasing positions),
+// so no permute runs before the product.  Each 128 x 16 chunk is gathered in
+// A's address order (the chunk map) in 16-byte loads of two entries: A's
+// lowest index bit is the lowest row or k bit, so it belongs to the chunk.
+// The chunk's K offset moves by a carrying add restricted to the K bits
+// (valid because they are in increasing positions).
+struct GatherA {
+  SkewMap mp;
+  Runs aM;
+  uint64_t maskK = 0, incK = 0;
+};
+
 // 128x128 workgroup tile, four waves of 64x64 (2x2 blocks of 32x32 MFMA
 // tiles), K staged through LDS 16 at a time; the next K tile is loaded into
 // registers while the current one is multiplied.  Planar LDS: re, im; the
 // 3M operand sums re+im are formed in registers after the LDS reads, which
 // keeps the kernel within 256 registers per lane (two waves per SIMD).
 // blockIdx.z selects a batch entry or a split-K slab through the strides sA,
-// sB, sC.
-template <int FORM>
+// sB, sC (GA = 0 only).
+template <int FORM, int GA>
 __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ A, const float2* __restrict__ B,
                                                  float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
                                                  int64_t sA, int64_t sB, int64_t sC, int64_t Mt, int64_t Nt,
-                                                 int chunk) {
+                                                 int chunk, const GatherA g) {
   constexpr int P = (FORM == TN_GEMM_3M) ? 3 : 2;
   constexpr int BM = 128, BN = 128, BK = 16, LD = BM + 2;
+  constexpr int LPT = 4;  // gathered A: 16-byte loads per thread per chunk
   __shared__ float As[2][BK][LD];
   __shared__ float Bs[2][BK][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -159,11 +175,37 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
   const float2* Ap = A + (bm + lrow) * K + lk;
   const float2* Bp = B + (bn + lrow) * K + lk;
   float4 ra[4], rb[4];
+  // gathered A: this thread's two entries per load (offset of the first
+  // from the chunk's first entry; LDS indices k * LD + m of both, packed in
+  // 16 bits each), the tile's row offset and the chunk's K offset
+  uint32_t eoff[GA ? LPT : 1], eidx[GA ? LPT : 1];
+  uint64_t abase = 0, kofs = 0;
+  float4 rg[GA ? LPT : 1];
+  if constexpr (GA != 0) {
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      uint64_t off, off1;
+      int m0, k0, m1, k1;
+      skew_split(g.mp, (j * 256 + tid) * 2, off, m0, k0);
+      skew_split(g.mp, (j * 256 + tid) * 2 + 1, off1, m1, k1);
+      eoff[j] = (uint32_t)off;
+      eidx[j] = (uint32_t)(k0 * LD + m0) | ((uint32_t)(k1 * LD + m1) << 16);
+    }
+    abase = dep((uint64_t)bm, g.aM);
+  }
+  auto load_a = [&]() {
+    if constexpr (GA != 0) {
+      const float2* base = A + (abase + kofs);
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) rg[j] = *reinterpret_cast<const float4*>(base + eoff[j]);
+    }
+  };
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    ra[j] = *reinterpret_cast<const float4*>(Ap + 2 * j);
+    if constexpr (GA == 0) ra[j] = *reinterpret_cast<const float4*>(Ap + 2 * j);
     rb[j] = *reinterpret_cast<const float4*>(Bp + 2 * j);
   }
+  load_a();
   const int c = lane & 31, kh = lane >> 5;
   // Adds (ADD false: stores) the running FP32 sums to C and restarts them.
   // Called every `chunk` K stages, where the staged operands have just been
@@ -209,14 +251,28 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      As[0][lk + 2 * j][lrow] = ra[j].x;
-      As[1][lk + 2 * j][lrow] = ra[j].y;
-      As[0][lk + 2 * j + 1][lrow] = ra[j].z;
-      As[1][lk + 2 * j + 1][lrow] = ra[j].w;
+      if constexpr (GA == 0) {
+        As[0][lk + 2 * j][lrow] = ra[j].x;
+        As[1][lk + 2 * j][lrow] = ra[j].y;
+        As[0][lk + 2 * j + 1][lrow] = ra[j].z;
+        As[1][lk + 2 * j + 1][lrow] = ra[j].w;
+      }
       Bs[0][lk + 2 * j][lrow] = rb[j].x;
       Bs[1][lk + 2 * j][lrow] = rb[j].y;
       Bs[0][lk + 2 * j + 1][lrow] = rb[j].z;
       Bs[1][lk + 2 * j + 1][lrow] = rb[j].w;
+    }
+    if constexpr (GA != 0) {
+      float* a0 = &As[0][0][0];
+      float* a1 = &As[1][0][0];
+#pragma unroll
+      for (int j = 0; j < LPT; ++j) {
+        const int i0 = (int)(eidx[j] & 0xffffu), i1 = (int)(eidx[j] >> 16);
+        a0[i0] = rg[j].x;
+        a1[i0] = rg[j].y;
+        a0[i1] = rg[j].z;
+        a1[i1] = rg[j].w;
+      }
     }
     if (chunk > 0 && it > 0 && it % chunk == 0) {
       if (first)
@@ -229,8 +285,12 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
     if (k0 + BK < k_len) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        ra[j] = *reinterpret_cast<const float4*>(Ap + k0 + BK + 2 * j);
+        if constexpr (GA == 0) ra[j] = *reinterpret_cast<const float4*>(Ap + k0 + BK + 2 * j);
         rb[j] = *reinterpret_cast<const float4*>(Bp + k0 + BK + 2 * j);
+      }
+      if constexpr (GA != 0) {
+        kofs = ((kofs | ~g.maskK) + g.incK) & g.maskK;
+        load_a();
       }
     }
 #pragma unroll
@@ -309,11 +369,11 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * splits));
     if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
-                         chunk);
+      hipLaunchKernelGGL((k_cgemm128<TN_GEMM_3M, 0>), grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
+                         chunk, GatherA{});
     else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
-                         chunk);
+      hipLaunchKernelGGL((k_cgemm128<TN_GEMM_4M, 0>), grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
+                         chunk, GatherA{});
     const int64_t n = M * N;
     hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
                        work, C, n, splits);
@@ -326,11 +386,11 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * batch));
     if (form == TN_GEMM_3M)
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
-                         chunk);
+      hipLaunchKernelGGL((k_cgemm128<TN_GEMM_3M, 0>), grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
+                         chunk, GatherA{});
     else
-      hipLaunchKernelGGL(k_cgemm128<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
-                         chunk);
+      hipLaunchKernelGGL((k_cgemm128<TN_GEMM_4M, 0>), grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N, Mt, Nt,
+                         chunk, GatherA{});
     return hipGetLastError();
   }
   if (N / GBN > 65535) return hipErrorInvalidValue;
@@ -339,6 +399,32 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
     hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
   else
     hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
+  return hipGetLastError();
+}
+
+static uint64_t dep_host(uint64_t x, const Runs& r) {
+  uint64_t o = 0;
+  for (int i = 0; i < r.n; ++i) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
+  return o;
+}
+
+hipError_t launch_gemm_c64_ga(const float2* A, const float2* B, float2* C, const IndexOp& idx, int form,
+                              hipStream_t s) {
+  if (!gemm_gather_ok(idx)) return hipErrorInvalidValue;
+  const int64_t M = (int64_t)1 << idx.nM, N = (int64_t)1 << idx.nN, K = (int64_t)1 << idx.nK;
+  GatherA g{};
+  skew_map(idx, 4, 0, &g.mp);
+  g.aM = idx.aM;
+  g.maskK = dep_host((uint64_t)(K - 1) & ~(uint64_t)15, idx.aK);
+  g.incK = K > 16 ? dep_host(16, idx.aK) : 0;
+  if (g.mp.pos[0] != 0) return hipErrorInvalidValue;  // A's lowest bit must belong to the chunk
+  const int chunk = kAccChain / 16;
+  const int64_t Mt = M / 128, Nt = N / 128;
+  const dim3 grid((unsigned)(Mt * Nt));
+  if (form == TN_GEMM_3M)
+    hipLaunchKernelGGL((k_cgemm128<TN_GEMM_3M, 1>), grid, dim3(256), 0, s, A, B, C, N, K, K, 0, 0, 0, Mt, Nt, chunk, g);
+  else
+    hipLaunchKernelGGL((k_cgemm128<TN_GEMM_4M, 1>), grid, dim3(256), 0, s, A, B, C, N, K, K, 0, 0, 0, Mt, Nt, chunk, g);
   return hipGetLastError();
 }
 

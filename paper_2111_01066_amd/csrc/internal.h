@@ -57,6 +57,7 @@ struct GemmOp {
   int32_t tile = 0;       // workgroup tile edge: 0 = chosen by shape, 64 or 128 (autotuner)
   int32_t split_max = 1;  // split-K workspace capacity in slabs
   int32_t occ = 0;        // FP16/BF16 128x128 kernel: waves per SIMD (0 = chosen by K, 1 or 2; autotuner)
+  int32_t gather_a = 0;   // 1: A is read in its stored layout through the op's idx.aM / idx.aK (complex64)
 };
 
 // Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],
@@ -210,6 +211,34 @@ inline int default_class(int nM, int nN, int nK) {
   if (m & (1u << kOpSkew)) return kOpSkew;
   if (m & (1u << kOpSkinny)) return kOpSkinny;
   return kOpGeneric;
+}
+// Position in the target of bit j of a value deposited by runs r (-1: none).
+inline int run_pos(const Runs& r, int j) {
+  for (int i = 0; i < r.n; ++i)
+    if (j >= r.src[i] && j < r.src[i] + r.len[i]) return r.dst[i] + (j - r.src[i]);
+  return -1;
+}
+// Complex64 GEMM steps whose large operand A (at least 2^kGatherMinLog2
+// entries) is not stored as [M bits, K bits] and whose sum has at least
+// 2^kGatherMinK terms read A in place instead of permuting it first, when
+// its layout admits that: 128 x 128 output tiles and chunks of 16 k (nM, nN
+// >= 7, nK >= 4), the chunk's 11 bits within A's low 32 positions, and the k
+// bits above 3 in increasing positions.
+constexpr int kGatherMinLog2 = 20;
+constexpr int kGatherMinK = 7;
+inline bool gemm_gather_ok(const IndexOp& idx) {
+  if (idx.nM < 7 || idx.nN < 7 || idx.nK < 4) return false;
+  for (int j = 0; j < 7; ++j) {
+    const int p = run_pos(idx.aM, j);
+    if (p < 0 || p >= 32) return false;
+  }
+  int prev = -1;
+  for (int j = 0; j < idx.nK; ++j) {
+    const int p = run_pos(idx.aK, j);
+    if (p < 0 || (j < 4 && p >= 32) || (j >= 4 && p <= prev)) return false;
+    if (j >= 4) prev = p;
+  }
+  return true;
 }
 // Planner entry (host only).  Returns TN_OK or an error code with a message.
 int build_plan(PlanCore& P, std::string& err);

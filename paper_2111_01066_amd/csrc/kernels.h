@@ -34,6 +34,11 @@ hipError_t launch_permute(int elem_bytes, const void* in, void* out, int rank, c
 hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t M, int64_t N, int64_t K,
                            int64_t batch, int form, hipStream_t s, float2* work = nullptr, int splits = 1,
                            int tile = 0);
+// complex64 GEMM whose A is read in its stored layout through idx.aM / idx.aK
+// (B is [N][K], C is [M][N]; 128x128 tiles, no K split): the planner's
+// alternative to permuting A first (gemm_gather_ok must hold).
+hipError_t launch_gemm_c64_ga(const float2* A, const float2* B, float2* C, const IndexOp& idx, int form,
+                              hipStream_t s);
 // scaled FP16/BF16 GEMM on half MFMA; C = A B^T * out_scale; max |A B^T| recorded in *maxslot.
 // tile: 0 auto, 64 or 128; occ (128 tiles): 0 auto, 1 or 2 waves per SIMD, 3 the
 // ping-pong 256x128 kernel (4M, M % 256 == 0, K per split % 32 == 0).

@@ -278,8 +278,15 @@ void make_json(PlanCore& P) {
     } else if (op.kind == kOpGemm) {
       js << ",\"M\":" << op.gemm.M << ",\"N\":" << op.gemm.N << ",\"K\":" << op.gemm.K << ",\"form\":" << op.gemm.form
          << ",\"split_k\":" << op.gemm.split_k << ",\"tile\":" << op.gemm.tile << ",\"split_max\":"
-         << op.gemm.split_max << ",\"occ\":" << op.gemm.occ << ",\"s_out\":" << op.s_out << ",\"w\":";
+         << op.gemm.split_max << ",\"occ\":" << op.gemm.occ << ",\"ga\":" << op.gemm.gather_a
+         << ",\"s_out\":" << op.s_out << ",\"w\":";
       json_ref(js, op.w);
+      if (op.gemm.gather_a) {
+        js << ",\"aM\":";
+        json_runs(js, op.idx.aM);
+        js << ",\"aK\":";
+        json_runs(js, op.idx.aK);
+      }
     } else {
       js << ",\"nM\":" << op.idx.nM << ",\"nN\":" << op.idx.nN << ",\"nK\":" << op.idx.nK << ",\"aM\":";
       json_runs(js, op.idx.aM);
@@ -634,6 +641,31 @@ int build_plan(PlanCore& P, std::string& err) {
       };
       std::vector<int> Kord;
       if (!k_low_block(La, Kord) && !k_low_block(Lb, Kord)) Kord = K;
+      // complex64: a large A that would need a permute is read in place by
+      // the GEMM, with the K bits in A's own order (B is permuted to match).
+      // Only for K >= 128: on shorter sums the in-place GEMM (128x128 tiles
+      // only) measured slower than the permute plus the tuned GEMM.
+      IndexOp gidx;
+      bool gather = false;
+      {
+        std::vector<int> wa = MA;
+        wa.insert(wa.end(), Kord.begin(), Kord.end());
+        if (!half && wa != La && ra >= kGatherMinLog2 && nK >= kGatherMinK) {
+          gidx.nM = nM;
+          gidx.nN = nN;
+          gidx.nK = nK;
+          std::vector<int> p;
+          for (int i = 0; i < nM; ++i) p.push_back(pos_in(La, MA[nM - 1 - i]));
+          bool ok = make_runs(p, &gidx.aM);
+          p.clear();
+          for (int i = 0; i < nK; ++i) p.push_back(pos_in(La, K[nK - 1 - i]));
+          ok = ok && make_runs(p, &gidx.aK);
+          if (ok && gemm_gather_ok(gidx)) {
+            gather = true;
+            Kord = K;
+          }
+        }
+      }
       std::vector<int> wantA = MA, wantB = NB;
       wantA.insert(wantA.end(), Kord.begin(), Kord.end());
       wantB.insert(wantB.end(), Kord.begin(), Kord.end());
@@ -643,7 +675,7 @@ int build_plan(PlanCore& P, std::string& err) {
         const std::vector<int>& have = side ? Lb : La;
         const std::vector<int>& want = side ? wantB : wantA;
         int ssa = side ? ib : ia;
-        if (have == want) continue;
+        if (have == want || (side == 0 && gather)) continue;
         Op op;
         op.kind = kOpPermute;
         op.step = t;
@@ -676,8 +708,13 @@ int build_plan(PlanCore& P, std::string& err) {
       // those kernels bound by LDS bandwidth)
       g.gemm.form = P.opts.gemm_form != TN_GEMM_AUTO ? P.opts.gemm_form : (half ? TN_GEMM_4M : TN_GEMM_3M);
       int gi = (int)P.ops.size();
+      if (gather) {
+        g.gemm.gather_a = 1;
+        g.gemm.tile = 128;
+        g.idx = gidx;
+      }
       // split K when the output has too few 128x128 tiles to fill the chip
-      if (nM >= 7 && nN >= 7) {
+      if (nM >= 7 && nN >= 7 && !gather) {
         const int64_t tiles = (int64_t)1 << (nM - 7 + nN - 7);
         int sp = 1;
         while (tiles * sp < 2048 && ((int64_t)1 << nK) / (sp * 2) >= 1024 && sp < 64 &&

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "elem.h"
+#include "gather.h"
 #include "kernels.h"
 
 namespace tnrcs {
@@ -64,24 +65,6 @@ __device__ __forceinline__ void skew_st_nt(E* p, E e) {
 constexpr int kSkewPM = 128;  // rows per pass
 constexpr int kSkewKC = 16;   // K staged per chunk (fewer when K is smaller)
 constexpr int kSkewLDA = 160;  // LDS k-row stride (floats): 128 rows + 32, so rows k and k+1 sit 32 banks apart
-constexpr int kSkewMaxV = 11;  // index bits of one chunk: 7 row bits + up to 4 k bits
-
-// Address order of one chunk: chunk element e (0 .. 2^v) has its bit i at
-// A position pos[i], and is row bit mb[i] (or -1) / k bit kb[i] (or -1) of
-// the chunk; the bits are sorted by A position.  Row m, k of the chunk sits
-// in LDS at k * kSkewLDA + (m ^ h), h = XOR of hk[i] over the set k bits i
-// and of hm[j] over the set row bits 5 + j: a swizzle that keeps the 32 rows
-// a matrix-core operand reads at one k in 32 distinct banks, and gives the
-// 32 entries that one half-wave stores (consecutive in address order)
-// distinct banks too.
-struct SkewMap {
-  int32_t v;
-  int8_t pos[kSkewMaxV];
-  int8_t mb[kSkewMaxV];
-  int8_t kb[kSkewMaxV];
-  int8_t hk[4];
-  int8_t hm[2];
-};
 
 // LDS of one workgroup (bytes): A chunk planes, B planes (resident: all of
 // K; else one chunk), B's K offset table, its N offsets, and A's offset of
@@ -91,29 +74,6 @@ static size_t skew_lds(int nK, int np, bool bres) {
   const size_t kc = (size_t)std::min<int64_t>(K, kSkewKC);
   const size_t kb = bres ? K : kc;
   return 2 * kc * kSkewLDA * 4 + 2 * kb * (np + 4) * 4 + K * 8 + 64 * 8 + (K / kc) * 8;
-}
-
-__device__ __forceinline__ int skew_h(const SkewMap& mp, int m, int k) {
-  int h = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if ((k >> i) & 1) h ^= mp.hk[i];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-    if ((m >> (5 + j)) & 1) h ^= mp.hm[j];
-  return h;
-}
-
-__device__ __forceinline__ void skew_split(const SkewMap& mp, int e, uint64_t& off, int& m, int& k) {
-  off = 0;
-  m = 0;
-  k = 0;
-  for (int i = 0; i < mp.v; ++i) {
-    const int b = (e >> i) & 1;
-    off |= (uint64_t)b << mp.pos[i];
-    if (mp.mb[i] >= 0) m |= b << mp.mb[i];
-    if (mp.kb[i] >= 0) k |= b << mp.kb[i];
-  }
 }
 
 // VEC consecutive chunk elements per load (VEC > 1: A's lowest log2(VEC)
@@ -596,14 +556,7 @@ static size_t skew_ph_lds(int K, int np) { return 2 * kSkewPM * kSkewHS * 2 + 2 
 
 bool skew_ok(const IndexOp& op) { return op.nN <= 6 && op.nK >= 1 && op.nK <= 10 && op.nM >= 7; }
 
-// Position in the target of bit j of a value deposited by runs r (-1: none).
-static int run_pos(const Runs& r, int j) {
-  for (int i = 0; i < r.n; ++i)
-    if (j >= r.src[i] && j < r.src[i] + r.len[i]) return r.dst[i] + (j - r.src[i]);
-  return -1;
-}
-
-static bool skew_map(const IndexOp& op, int kcb, int lv, SkewMap* mp) {
+bool skew_map(const IndexOp& op, int kcb, int lv, SkewMap* mp) {
   struct Var {
     int pos, m, k;
   };

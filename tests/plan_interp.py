@@ -67,7 +67,11 @@ class PlanInterpreter:
             elif op["kind"] == 1:  # gemm
                 rb, ob = self.region(op["b"])
                 M, N, K = op["M"], op["N"], op["K"]
-                A = ra[oa:oa + M * K].reshape(M, K)
+                if op.get("ga"):  # A read in its stored layout
+                    Ai = dep(np.arange(M), op["aM"])[:, None] | dep(np.arange(K), op["aK"])[None, :]
+                    A = ra[oa + Ai]
+                else:
+                    A = ra[oa:oa + M * K].reshape(M, K)
                 B = rb[ob:ob + N * K].reshape(N, K)
                 assert not np.isnan(A).any() and not np.isnan(B).any()
                 rc[oc:oc + M * N] = (A @ B.T).reshape(-1)

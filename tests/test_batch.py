@@ -277,12 +277,12 @@ def test_forced_pingpong_gemm_vs_oracle(tmp_path, dtype):
 def test_config5_circuits_in_one_batch_vs_oracle():
     """Four of the 512 frozen config-5 circuits, scaled FP16 in one batch,
     against the oracle's pairwise FP64 contraction of the same order: 5
-    (31 qubits, 10 cycles), 44 and 54 (28 qubits, 10 cycles), and 456 (28
-    qubits, 12 cycles, one sliced wire, 2^28-entry intermediates; about
+    (31 qubits, 10 cycles), 44 and 54 (28 qubits, 10 cycles), and 494 (32
+    qubits, 17 cycles, one sliced wire, 2^27-entry intermediates; about
     1e12 flop for the oracle)."""
     t = config5_table()
-    cand = [5, 44, 54, 456]
-    assert np.diff(t["sliced_off"])[456] == 1
+    cand = [5, 44, 54, 494]
+    assert np.diff(t["sliced_off"])[494] == 1
     ws_list = config5(indices=cand, table=t)
     cases = []
     for w in ws_list:

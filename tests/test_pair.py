@@ -67,7 +67,21 @@ TILED = [
 # permuted to [free wires, K] so that consecutive k are adjacent in memory
 ALIGN = [([20, 21, 22] + list(range(12)), [30, 31, 32] + [5, 0, 9, 2, 11, 7, 1, 4, 10, 3, 8, 6],
           [20, 21, 22, 30, 31, 32])]
-CASES = CASES + TILED + ALIGN
+# dense with an A of 2^20+ entries whose contracted wires are not its lowest
+# block and at least 128 terms: in complex64 the GEMM reads A in place (no
+# permute of A); K interleaved with M, K above M, and K split around M in
+# scattered order
+GATHER = [
+    ([600, 0, 601, 602, 1, 603, 2, 604, 605, 3, 606, 607, 4, 608, 609, 5, 610, 611, 6, 612],
+     list(range(700, 707)) + [3, 1, 0, 2, 6, 5, 4], list(range(600, 613)) + list(range(700, 707))),
+    ([600, 0, 601, 602, 1, 603, 2, 604, 605, 3, 606, 607, 4, 608, 609, 5, 610, 611, 6, 612, 7, 613],
+     list(range(700, 707)) + [3, 1, 0, 2, 6, 7, 5, 4], list(range(600, 614)) + list(range(700, 707))),
+    (list(range(7)) + list(range(620, 634)), [0, 1, 2, 3, 4, 5, 6] + list(range(720, 727)),
+     list(range(620, 634)) + list(range(720, 727))),
+    ([8, 0] + list(range(640, 652)) + [7, 1, 6, 2, 5, 3, 4],
+     list(range(740, 748)) + [4, 3, 5, 2, 6, 1, 7, 0, 8], list(range(640, 652)) + list(range(740, 748))),
+]
+CASES = CASES + TILED + ALIGN + GATHER
 
 
 def _rand(rng, r):
@@ -126,6 +140,20 @@ def test_pair_splitk_aligns_scattered_operand(la, lb, lc):
     assert ops[0]["a"] == [4, 0]  # the caller's B
     run = ops[1]["bK"][0]
     assert run[0] == 0 and run[1] == 0 and run[2] == 12  # all 12 k bits low and in order
+    pp.close()
+
+
+@pytest.mark.parametrize("la,lb,lc", GATHER)
+def test_pair_gather_cases_read_a_in_place(la, lb, lc):
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+    ops = pp.json()["ops"]
+    g = [o for o in ops if o["kind"] == 1]
+    assert len(g) == 1 and g[0]["ga"] == 1 and g[0]["a"] == [3, 0]  # the caller's A, not a permuted copy
+    assert all(o["a"] != [3, 0] for o in ops if o["kind"] == 0)
+    pp.close()
+    # scaled storage keeps the permute of A
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True, dtype="f16s")
+    assert all(o.get("ga", 0) == 0 for o in pp.json()["ops"])
     pp.close()
 
 
