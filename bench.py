@@ -521,11 +521,29 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
     log(f"[bench] batch: one graph launch {t_b:.3f} s ({flops / t_b / 1e12:.1f} complex TFLOP/s), graph built in "
         f"{t_build:.2f} s, identical to plan-by-plan: {same}, flags {flags}")
     b.close()
+    # where the batch time goes: every op of every plan timed alone (HIP
+    # events, slice 0) times the plan's slice count, split by the op's size
+    scratch = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    busy = small = 0.0
+    for i, p in enumerate(plans):
+        ops = p.json()["ops"]
+        ms = p.profile(0, scratch)
+        for j, t_op in enumerate(ms):
+            o = ops[j] if j < len(ops) else {}
+            out_log2 = (o["rank"] if o.get("kind") == 0 else
+                        (int(np.log2(o["M"] * o["N"])) if o.get("kind") == 1 else o.get("nM", 0) + o.get("nN", 0)))
+            busy += t_op * n_sl[i] / 1e3
+            if out_log2 < 20:
+                small += t_op * n_sl[i] / 1e3
+    log(f"[bench] batch: kernels alone {busy:.3f} s ({busy / t_b:.1%} of the one-graph time), "
+        f"{small:.3f} s of it in kernels with fewer than 2^20 outputs")
     for p in plans:
         p.close()
     del arena
     torch.cuda.empty_cache()
     return {"circuits": len(plans), "of": int(len(t["S"])), "max_order_flops": cap, "dtype": dtype,
+            "kernel_time_s": busy, "kernel_time_over_one_graph": busy / t_b, "small_kernel_time_s": small,
+            "time_to_amplitudes_with_plan_s": t_plan + t_b,
             "slices": int(sum(n_sl)), "kernels": kernels, "flops": flops, "arena_bytes": int(need),
             "plan_tune_calibrate_s": t_plan, "graph_build_s": t_build,
             "plan_by_plan_s": t_seq, "plan_by_plan_complex_tflops": flops / t_seq / 1e12,

@@ -323,10 +323,11 @@ int tn_permute(const void* in, void* out, int32_t elem_bytes, int32_t rank, cons
  * (complex64, row-major, A: M x K, B: N x K, C: M x N, batch strides
  * M*K, N*K, M*N elements).  form = TN_GEMM_4M or TN_GEMM_3M.  M, N multiples
  * of 64 and K a multiple of 16 (the planner only emits such shapes; other
- * shapes are routed to the other kernels).  splits > 1 (batch 1, M and N
- * multiples of 128, K a multiple of 16*splits) splits K into slabs written to
- * `work` (device, splits*M*N complex64, caller-owned) and summed in slab
- * order; work may be NULL when splits <= 1. */
+ * shapes are routed to the other kernels).  splits > 1 (batch 1, K a
+ * multiple of 16*splits; 128x128 tiles when M and N are multiples of 128,
+ * else 64x64) splits K into slabs written to `work` (device, splits*M*N
+ * complex64, caller-owned) and summed in slab order in FP64; work may be
+ * NULL when splits <= 1. */
 int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
                  int64_t batch, int32_t form, void* work, int32_t splits, void* stream);
 

@@ -375,6 +375,7 @@ static int tune_plan(tn_plan_s* p) {
 constexpr int kFuseMaxK = 6;
 constexpr int64_t kClassTuneMaxBytes = (int64_t)48 << 30;
 constexpr int kGatherTuneLog2 = 22;
+constexpr int kGatherTuneMaxK = 16;  // nor on sums of 2^16 terms or more (one output per thread)
 
 // Average time of one run of a one-step plan's ops in class `cls` (INFINITY
 // when the step does not fit the budget); builds, runs and frees the plan.
@@ -471,9 +472,10 @@ static int tune_classes(PlanCore& P, bool measure) {
     std::vector<int> cand;
     // the gathered kernel (one output per thread, operands re-read per
     // output) is a candidate only for steps of at most 2^kGatherTuneLog2
-    // outputs: on larger ones it loses to every other class by far, and
-    // timing it would dominate the tuning time
-    const bool big = st.nM + st.nN > kGatherTuneLog2;
+    // outputs and sums shorter than 2^kGatherTuneMaxK: beyond that it loses
+    // to every other class by far, and timing it would dominate the tuning
+    // time
+    const bool big = st.nM + st.nN > kGatherTuneLog2 || st.nK >= kGatherTuneMaxK;
     if (valid & (1u << kOpGemm)) {
       if (st.nK > kFuseMaxK) continue;
       cand = {kOpGemm};
@@ -1192,8 +1194,8 @@ int tn_cgemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N, in
   if (form != TN_GEMM_4M && form != TN_GEMM_3M) return fail(TN_E_ARG, "form must be TN_GEMM_4M or TN_GEMM_3M");
   if (!gemm_shape_ok(M, N, K) || batch < 0)
     return fail(TN_E_ARG, "shape not supported: M, N multiples of 64, K a multiple of 16");
-  if (splits > 1 && (!work || batch != 1 || M % 128 || N % 128 || K % (16 * (int64_t)splits)))
-    return fail(TN_E_ARG, "split-K needs work, batch 1, M and N multiples of 128, K a multiple of 16*splits");
+  if (splits > 1 && (!work || batch != 1 || K % (16 * (int64_t)splits)))
+    return fail(TN_E_ARG, "split-K needs work, batch 1 and K a multiple of 16*splits");
   hipError_t e = launch_gemm_c64((const float2*)A, (const float2*)B, (float2*)C, M, N, K, batch, form,
                                  (hipStream_t)stream, (float2*)work, splits < 1 ? 1 : splits);
   if (e != hipSuccess) return hip_fail(e, "gemm kernel");

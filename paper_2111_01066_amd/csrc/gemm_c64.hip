@@ -23,19 +23,21 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 64, GBN = 64, GBK = 16;
 
+// blockIdx.z selects a batch entry or a split-K slab through the strides sA,
+// sB, sC; each sums k_len terms of rows that are K long.
 template <int FORM>
 __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, const float2* __restrict__ B,
-                                              float2* __restrict__ C, int64_t M, int64_t N, int64_t K,
-                                              int chunk) {
+                                              float2* __restrict__ C, int64_t N, int64_t K, int64_t k_len,
+                                              int64_t sA, int64_t sB, int64_t sC, int chunk) {
   __shared__ float As[2][GBK][GBM + 4];
   __shared__ float Bs[2][GBK][GBN + 4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t bm = (int64_t)blockIdx.x * GBM, bn = (int64_t)blockIdx.y * GBN;
   const int64_t z = blockIdx.z;
-  A += z * M * K;
-  B += z * N * K;
-  C += z * M * N;
+  A += z * sA;
+  B += z * sB;
+  C += z * sC;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   floatx16 c0 = {}, c1 = {}, c2 = {};
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(256) void k_cgemm(const float2* __restrict__ A, con
   };
   bool first = true;
   int it = 0;
-  for (int64_t k0 = 0; k0 < K; k0 += GBK, ++it) {
+  for (int64_t k0 = 0; k0 < k_len; k0 += GBK, ++it) {
     if (chunk > 0 && it > 0 && it % chunk == 0) {
       if (first)
         flush(std::false_type{});
@@ -364,8 +366,22 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
   const bool big = fits128 && tile != 64;
   const int chunk = kAccChain / 16;  // K stages of the 128x128 kernel per FP32 chain
   if (splits > 1) {
-    if (batch != 1 || !work || !big || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
+    if (batch != 1 || !work || K % (16 * splits) != 0 || splits > 65535) return hipErrorInvalidValue;
     const int64_t kl = K / splits;
+    const int64_t n = M * N;
+    if (!big) {  // 64x64 tiles, one slab per blockIdx.z
+      if (N / GBN > 65535) return hipErrorInvalidValue;
+      dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)splits);
+      if (form == TN_GEMM_3M)
+        hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, n,
+                           kAccChain / GBK);
+      else
+        hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, n,
+                           kAccChain / GBK);
+      hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
+                         work, C, n, splits);
+      return hipGetLastError();
+    }
     const int64_t Mt = M / 128, Nt = N / 128;
     dim3 grid((unsigned)(Mt * Nt * splits));
     if (form == TN_GEMM_3M)
@@ -374,7 +390,6 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
     else
       hipLaunchKernelGGL((k_cgemm128<TN_GEMM_4M, 0>), grid, dim3(256), 0, s, A, B, work, N, K, kl, kl, kl, M * N, Mt, Nt,
                          chunk, GatherA{});
-    const int64_t n = M * N;
     hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
                        work, C, n, splits);
     return hipGetLastError();
@@ -396,9 +411,11 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
   if (N / GBN > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)(M / GBM), (unsigned)(N / GBN), (unsigned)batch);
   if (form == TN_GEMM_3M)
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_3M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N,
+                       kAccChain / GBK);
   else
-    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, M, N, K, kAccChain / GBK);
+    hipLaunchKernelGGL(k_cgemm<TN_GEMM_4M>, grid, dim3(256), 0, s, A, B, C, N, K, K, M * K, N * K, M * N,
+                       kAccChain / GBK);
   return hipGetLastError();
 }
 

@@ -186,16 +186,19 @@ void make_json(PlanCore& P);
 
 // Kernel classes of a step with 2^nM x 2^nN outputs over 2^nK terms.  dense
 // (permutes + MFMA GEMM): both free extents at least 64 (the smallest GEMM
-// tile) and K at least 16; split-K: at most 64 outputs; skewed (Supplement,
+// tile) and K at least 16; split-K: at most 64 outputs, or up to
+// 2^kSplitKMaxOutLog2 outputs (run as groups of 64) over at least 2^12
+// terms; skewed (Supplement,
 // CPU-architecture section): few outputs per row of the large operand, in
 // two kernels: on the vector units with the small operand in LDS (at most
 // 16 outputs per row, 2^(nK+nN) <= 2^kSkinnyMaxLog2 entries), and on the
 // matrix cores (at most 64 outputs per row, 2 <= K <= 2^10, at least 128
 // rows); gathered: always valid.  Bit mask over OpKind.
+constexpr int kSplitKMaxOutLog2 = 12;
 inline unsigned step_classes(int nM, int nN, int nK) {
   unsigned m = 1u << kOpGeneric;
   if (nM >= 6 && nN >= 6 && nK >= 4) m |= 1u << kOpGemm;
-  if (nM + nN <= 6 && nK >= 4) m |= 1u << kOpSplitK;
+  if ((nM + nN <= 6 && nK >= 4) || (nM + nN <= kSplitKMaxOutLog2 && nK >= 12)) m |= 1u << kOpSplitK;
   if (nN <= 4 && nK + nN <= kSkinnyMaxLog2 && nM >= 8) m |= 1u << kOpSkinny;
   if (nN <= 6 && nK >= 1 && nK <= 10 && nM >= 7) m |= 1u << kOpSkew;
   return m;

@@ -708,9 +708,19 @@ __device__ __forceinline__ void load_run(const E* p, float2 (&out)[VK]) {
 
 // VK > 1: each thread takes VK consecutive k per step (both operands' lowest
 // log2(VK) k bits are their lowest bits, in order), read in 16-byte loads.
+// Groups (more than 64 outputs): blockIdx.y = group (im, in) of 2^op.nM x
+// 2^op.nN outputs, whose A and B start at dep(im << op.nM, gA) and
+// dep(in << op.nN, gB) (the full maps); 2^gn_bits groups along n.  Block
+// partials go to part[(group * gridDim.x + block) * nout + output].
+struct SplitGroups {
+  Runs gA, gB;
+  int32_t gn_bits = 0;
+};
+
 template <int NN, int VK, typename E>
 __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, const E* __restrict__ B,
-                                                    float2* __restrict__ part, const IndexOp op) {
+                                                    float2* __restrict__ part, const IndexOp op,
+                                                    const SplitGroups gr) {
   // outputs (m, n): m < nm = 2^nM <= 64 / NN, n < NN = 2^nN; each k loads
   // every A entry (one per m) and every B entry (one per n) once
   constexpr int NM = 64 / NN;
@@ -718,6 +728,12 @@ __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, co
   __shared__ float red[2][256];
   const int nm = 1 << op.nM;
   const int tid = threadIdx.x;
+  {
+    const uint64_t grp = blockIdx.y;
+    A += dep((grp >> gr.gn_bits) << op.nM, gr.gA);
+    B += dep((grp & ((1ull << gr.gn_bits) - 1)) << op.nN, gr.gB);
+    part += (int64_t)blockIdx.y * gridDim.x * (nm * NN);
+  }
   if (tid < nm) am[tid] = dep((uint64_t)tid, op.aM);
   if (tid < NN) bn[tid] = dep((uint64_t)tid, op.bN);
   __syncthreads();
@@ -807,10 +823,19 @@ __global__ __launch_bounds__(256) void k_splitk_part(const E* __restrict__ A, co
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__ part, int nblk, int nout,
-                                                     E* __restrict__ C, float out_scale, float* maxslot) {
+                                                     E* __restrict__ C, float out_scale, float* maxslot, int ln_sub,
+                                                     int ln_row, int lm_sub, int gn_bits) {
   __shared__ float red[2][256];
   const int tid = threadIdx.x;
   float mx = 0.f;
+  {
+    // group blockIdx.x = (im, in): its block partials, and its outputs'
+    // first row and column in C
+    const int64_t grp = blockIdx.x;
+    part += grp * nblk * nout;
+    const int64_t im = grp >> gn_bits, in = grp & ((1 << gn_bits) - 1);
+    C += ((im << lm_sub) << ln_row) | (in << ln_sub);
+  }
   for (int o = 0; o < nout; ++o) {
     float r = 0.f, i = 0.f;
     for (int g = tid; g < nblk; g += 256) {
@@ -830,7 +855,10 @@ __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__
     }
     if (tid == 0) {
       mx = mag_max(mx, red[0][0], red[1][0]);
-      C[o] = from_f2<E>(red[0][0] * out_scale, red[1][0] * out_scale);
+      // output o = (i, j) of the group (j < 2^ln_sub) sits at row i, column j
+      // of C, whose rows hold 2^ln_row entries
+      C[((int64_t)(o >> ln_sub) << ln_row) | (o & ((1 << ln_sub) - 1))] =
+          from_f2<E>(red[0][0] * out_scale, red[1][0] * out_scale);
     }
     __syncthreads();
   }
@@ -840,38 +868,69 @@ __global__ __launch_bounds__(256) void k_splitk_final(const float2* __restrict__
 int64_t splitk_blocks(const IndexOp& op) { return splitk_grid(op.nK); }
 
 template <int VK, typename E>
-static void launch_splitk_v(const E* A, const E* B, float2* part, const IndexOp& op, dim3 grid, hipStream_t s) {
+static void launch_splitk_v(const E* A, const E* B, float2* part, const IndexOp& op, const SplitGroups& gr,
+                            dim3 grid, hipStream_t s) {
   const dim3 blk(256);
   switch (op.nN) {
-    case 0: hipLaunchKernelGGL((k_splitk_part<1, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 1: hipLaunchKernelGGL((k_splitk_part<2, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 2: hipLaunchKernelGGL((k_splitk_part<4, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 3: hipLaunchKernelGGL((k_splitk_part<8, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 4: hipLaunchKernelGGL((k_splitk_part<16, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    case 5: hipLaunchKernelGGL((k_splitk_part<32, VK, E>), grid, blk, 0, s, A, B, part, op); break;
-    default: hipLaunchKernelGGL((k_splitk_part<64, VK, E>), grid, blk, 0, s, A, B, part, op); break;
+    case 0: hipLaunchKernelGGL((k_splitk_part<1, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    case 1: hipLaunchKernelGGL((k_splitk_part<2, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    case 2: hipLaunchKernelGGL((k_splitk_part<4, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    case 3: hipLaunchKernelGGL((k_splitk_part<8, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    case 4: hipLaunchKernelGGL((k_splitk_part<16, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    case 5: hipLaunchKernelGGL((k_splitk_part<32, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
+    default: hipLaunchKernelGGL((k_splitk_part<64, VK, E>), grid, blk, 0, s, A, B, part, op, gr); break;
   }
+}
+
+// The map of value bits 0 .. bits-1 only.
+static Runs low_runs(const Runs& r, int bits) {
+  Runs o{};
+  for (int i = 0; i < r.n; ++i) {
+    if (r.src[i] >= bits) continue;
+    o.src[o.n] = r.src[i];
+    o.dst[o.n] = r.dst[i];
+    o.len[o.n] = (int8_t)std::min<int>(r.len[i], bits - r.src[i]);
+    ++o.n;
+  }
+  return o;
 }
 
 template <typename E>
 static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const IndexOp& op, float* maxslot,
                             hipStream_t s) {
-  const int nout = 1 << (op.nM + op.nN);
   const int64_t g = splitk_blocks(op);
   // 16-byte runs of k when both operands hold their lowest k bits lowest
   constexpr int VK = 16 / (int)sizeof(E), LV = VK == 4 ? 2 : 1;
   auto low = [&](const Runs& r) { return r.n >= 1 && r.src[0] == 0 && r.dst[0] == 0 && r.len[0] >= LV; };
-  if (op.nK >= LV && low(op.aK) && low(op.bK))
-    launch_splitk_v<VK>(A, B, part, op, dim3((unsigned)g), s);
+  const bool vec = op.nK >= LV && low(op.aK) && low(op.bK);
+  // more than 64 outputs: groups of 2^gm x 2^gn2 = 64 outputs (rows m and
+  // columns n of C), all in one launch (blockIdx.y), each re-reading its
+  // rows of A and B
+  const int gn = std::min(op.nN, 3), gm = std::min(op.nM, 6 - gn);
+  const int gn2 = std::min(op.nN, 6 - gm);
+  IndexOp sub = op;
+  sub.nM = gm;
+  sub.nN = gn2;
+  sub.aM = low_runs(op.aM, gm);
+  sub.bN = low_runs(op.bN, gn2);
+  SplitGroups gr;
+  gr.gA = op.aM;
+  gr.gB = op.bN;
+  gr.gn_bits = op.nN - gn2;
+  const int nout = 1 << (gm + gn2);
+  const unsigned groups = 1u << (op.nM - gm + op.nN - gn2);
+  const dim3 grid((unsigned)g, groups);
+  if (vec)
+    launch_splitk_v<VK>(A, B, part, sub, gr, grid, s);
   else
-    launch_splitk_v<1>(A, B, part, op, dim3((unsigned)g), s);
-  hipLaunchKernelGGL(k_splitk_final<E>, dim3(1), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot);
+    launch_splitk_v<1>(A, B, part, sub, gr, grid, s);
+  hipLaunchKernelGGL(k_splitk_final<E>, dim3(groups), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot,
+                     gn2, op.nN, gm, gr.gn_bits);
 }
 
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s) {
-  const int nout = 1 << (op.nM + op.nN);
-  if (nout > 64) return hipErrorInvalidValue;
+  if (op.nM + op.nN > kSplitKMaxOutLog2) return hipErrorInvalidValue;
   if (dtype == TN_DTYPE_F16S)
     launch_splitk_t<cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, part, op, maxslot, s);
   else if (dtype == TN_DTYPE_BF16S)

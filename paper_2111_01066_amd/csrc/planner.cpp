@@ -713,9 +713,11 @@ int build_plan(PlanCore& P, std::string& err) {
         g.gemm.tile = 128;
         g.idx = gidx;
       }
-      // split K when the output has too few 128x128 tiles to fill the chip
-      if (nM >= 7 && nN >= 7 && !gather) {
-        const int64_t tiles = (int64_t)1 << (nM - 7 + nN - 7);
+      // split K when the output has too few tiles (128x128, or 64x64 when an
+      // extent is 64) to fill the chip
+      if (nM >= 6 && nN >= 6 && !gather) {
+        const int tl = (nM >= 7 && nN >= 7) ? 7 : 6;
+        const int64_t tiles = (int64_t)1 << (nM - tl + nN - tl);
         int sp = 1;
         while (tiles * sp < 2048 && ((int64_t)1 << nK) / (sp * 2) >= 1024 && sp < 64 &&
                ((int64_t)sp * 2 << (nM + nN)) <= ((int64_t)1 << 28))

@@ -101,7 +101,6 @@ int tune_gemm(int dtype, GemmOp& g, const void* a, const void* b, void* c, float
     if (sp > 1 && (!w || g.K % (16 * sp) != 0)) continue;
     for (int tile : {64, 128}) {
       if (tile == 128 && !fits128) continue;
-      if (dtype == TN_DTYPE_C64 && sp > 1 && tile == 64) continue;  // c64 slabs use the 128 kernel
       if (dtype != TN_DTYPE_C64 && tile == 128) {
         variants.push_back({tile, sp, 1});
         variants.push_back({tile, sp, 2});

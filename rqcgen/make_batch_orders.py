@@ -3,11 +3,11 @@
 (n uniform on 24..40 qubits, d uniform on 10..20 cycles, seeds 1000 + i),
 each with its 6 highest-numbered qubits open.
 
-Per circuit the candidates are greedy orders (seeds 0..3) and recursive
-bisection orders (seeds 0..2); each is sliced to the per-tensor bound
-2^S with S = 28, raised one at a time while more than 8 wires would be
-sliced; the candidate with the lowest total flop count (per-slice flops x
-slice count) is kept.
+Per circuit: recursive-bisection trees (seeds 0..2) are reconfigured,
+sliced to the per-tensor bound 2^S with reconfiguration between slicing
+steps (rqcgen.optimize; S = 28, raised one at a time while more than 8
+wires would be sliced), and the one with the lowest total cost in the
+kernel time model (scaled FP16 storage: alpha = 100) is kept.
 
   python -m rqcgen.make_batch_orders [--count 512] [--jobs 6]
 """
@@ -23,35 +23,35 @@ import numpy as np
 
 from .circuit import uneven_circuit
 from .network import network_structure
-from .order import bisection_order, greedy_order, order_stats, slice_to_fit
+from .optimize import CostModel, _Net, optimize_tree
 from .workloads import DATA
 
 S_BASE = 28
 K_MAX = 8
+ALPHA = 100.0
 
 
 def _best_order(i: int):
     c = uneven_circuit(i)
     open_q = list(range(c.n_qubits - 6, c.n_qubits))
     ns = network_structure(c, open_q)
-    cands = [("greedy", sd, greedy_order(ns, seed=sd)) for sd in range(4)]
-    cands += [("bisect", sd, bisection_order(ns, seed=sd)) for sd in range(3)]
+    net = _Net(ns)
     best = None
-    for kind, sd, pairs in cands:
+    for sd in range(3):
         S = S_BASE
         while True:
-            sliced = slice_to_fit(ns, pairs, S)
-            if len(sliced) <= K_MAX:
+            t = net.bisection_tree(sd, 0.35, 0.65, 8, True)
+            r = optimize_tree(net, t, CostModel(ALPHA, S), m=8, source=f"bisect:{sd}")
+            if len(r.sliced) <= K_MAX:
                 break
             S += 1
-        st = order_stats(ns, pairs, sliced)
-        key = (st.total_flops, st.flops_per_slice)
+        key = (r.total_cost, r.total_flops)
         if best is None or key < best[0]:
-            best = (key, kind, sd, pairs, sliced, S, st)
-    _, kind, sd, pairs, sliced, S, st = best
-    return dict(i=i, n=c.n_qubits, d=c.cycles, pairs=np.asarray(pairs, dtype=np.int32).reshape(-1, 2),
-                sliced=np.asarray(sliced, dtype=np.int32), S=S, total=st.total_flops,
-                per_slice=st.flops_per_slice, log2_max=st.log2_max, method=f"{kind}:{sd}")
+            best = (key, r, S)
+    _, r, S = best
+    return dict(i=i, n=c.n_qubits, d=c.cycles, pairs=np.asarray(r.pairs, dtype=np.int32).reshape(-1, 2),
+                sliced=np.asarray(r.sliced, dtype=np.int32), S=S, total=r.total_flops,
+                per_slice=r.flops_per_slice, log2_max=r.log2_max, method=r.source)
 
 
 def main():

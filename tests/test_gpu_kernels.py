@@ -106,8 +106,11 @@ def test_cgemm_matches_fp64(form, M, N, K, batch):
 
 
 @pytest.mark.parametrize("form", ["4m", "3m"])
-@pytest.mark.parametrize("M,N,K,splits", [(128, 128, 4096, 4), (256, 128, 65536, 16), (128, 256, 2048, 8)])
+@pytest.mark.parametrize("M,N,K,splits", [(128, 128, 4096, 4), (256, 128, 65536, 16), (128, 256, 2048, 8),
+                                           (192, 64, 32768, 16), (64, 320, 8192, 4)])
 def test_cgemm_split_k(form, M, N, K, splits):
+    """128x128-tile slabs, and 64x64-tile slabs when an extent is not a
+    multiple of 128."""
     rng = np.random.default_rng(M * 7 + K)
     A = _rand_c64(rng, M, K)
     B = _rand_c64(rng, N, K)

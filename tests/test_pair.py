@@ -81,7 +81,18 @@ GATHER = [
     ([8, 0] + list(range(640, 652)) + [7, 1, 6, 2, 5, 3, 4],
      list(range(740, 748)) + [4, 3, 5, 2, 6, 1, 7, 0, 8], list(range(640, 652)) + list(range(740, 748))),
 ]
-CASES = CASES + TILED + ALIGN + GATHER
+# long sums into more than 64 outputs: split-K over groups of 64 outputs
+# (512 and 2048 outputs; one operand's contracted wires scattered), and a
+# GEMM with a 64-wide extent whose K is split over 64x64-tile slabs
+WIDE = [
+    ([800, 801, 802, 803, 804] + list(range(12)), [810, 811, 812, 813] + list(range(12)),
+     [800, 801, 802, 803, 804, 810, 811, 812, 813]),
+    ([820, 821, 822, 823, 824, 825] + list(range(12)), [5, 830, 0, 831, 9, 832, 833, 834, 2, 11, 1, 3, 4, 6, 7, 8, 10],
+     [830, 820, 831, 821, 832, 822, 833, 823, 834, 824, 825]),
+    (list(range(900, 909)) + list(range(14)), list(range(910, 916)) + list(range(14)),
+     list(range(900, 909)) + list(range(910, 916))),
+]
+CASES = CASES + TILED + ALIGN + GATHER + WIDE
 
 
 def _rand(rng, r):
@@ -155,6 +166,16 @@ def test_pair_gather_cases_read_a_in_place(la, lb, lc):
     pp = tnrcs.PairPlan(la, lb, lc, dry_run=True, dtype="f16s")
     assert all(o.get("ga", 0) == 0 for o in pp.json()["ops"])
     pp.close()
+
+
+def test_pair_wide_cases_plan_split_k_and_split_gemm():
+    kinds = []
+    for la, lb, lc in WIDE:
+        pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
+        kinds.append([(o["kind"], o.get("split_k", 0)) for o in pp.json()["ops"] if o["kind"] != 0])
+        pp.close()
+    assert kinds[0] == [(4, 0)] and kinds[1] == [(4, 0)]
+    assert kinds[2][0][0] == 1 and kinds[2][0][1] > 1  # a 512 x 64 GEMM, K split
 
 
 def test_pair_rejects_bad_labels():

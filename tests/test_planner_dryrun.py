@@ -195,7 +195,7 @@ def _valid(nM, nN, nK):
     v = {2}
     if nM >= 6 and nN >= 6 and nK >= 4:
         v.add(1)
-    if nM + nN <= 6 and nK >= 4:
+    if (nM + nN <= 6 and nK >= 4) or (nM + nN <= 12 and nK >= 12):
         v.add(4)
     if nN <= 4 and nK + nN <= 11 and nM >= 8:
         v.add(3)
@@ -207,7 +207,7 @@ def _valid(nM, nN, nK):
 def _class_candidates(st):
     nM, nN, nK = st["nM"], st["nN"], st["nK"]
     v = _valid(nM, nN, nK)
-    big = nM + nN > 22  # the gathered kernel is not timed on large steps
+    big = nM + nN > 22 or nK >= 16  # the gathered kernel is not timed on large steps or long sums
     if 1 in v:
         if nK > 6:
             return []
