@@ -532,9 +532,9 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
             o = ops[j] if j < len(ops) else {}
             out_log2 = (o["rank"] if o.get("kind") == 0 else
                         (int(np.log2(o["M"] * o["N"])) if o.get("kind") == 1 else o.get("nM", 0) + o.get("nN", 0)))
-            busy += t_op * n_sl[i] / 1e3
+            busy += float(t_op) * n_sl[i] / 1e3
             if out_log2 < 20:
-                small += t_op * n_sl[i] / 1e3
+                small += float(t_op) * n_sl[i] / 1e3
     log(f"[bench] batch: kernels alone {busy:.3f} s ({busy / t_b:.1%} of the one-graph time), "
         f"{small:.3f} s of it in kernels with fewer than 2^20 outputs")
     for p in plans:

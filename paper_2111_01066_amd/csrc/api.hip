@@ -238,9 +238,11 @@ static int launch_op(tn_plan_s* p, const Op& op, hipStream_t s) {
       HIP_TRY(launch_permute(p->eb, a, c, op.perm.rank, op.perm.perm, 1, s), "permute kernel");
       break;
     case kOpGemm:
-      if (op.gemm.gather_a)
+      if (op.gemm.gather_a && dt == TN_DTYPE_C64)
         HIP_TRY(launch_gemm_c64_ga((const float2*)a, (const float2*)b, (float2*)c, op.idx, op.gemm.form, s),
                 "gemm kernel (A in place)");
+      else if (op.gemm.gather_a)
+        HIP_TRY(launch_gemm_half_ga(dt, a, b, c, op.idx, op.gemm.out_scale, slot, s), "half gemm kernel (A in place)");
       else if (dt == TN_DTYPE_C64)
         HIP_TRY(launch_gemm_c64((const float2*)a, (const float2*)b, (float2*)c, op.gemm.M, op.gemm.N, op.gemm.K, 1,
                                 op.gemm.form, s, op.gemm.split_k > 1 ? w : nullptr, op.gemm.split_k, op.gemm.tile),

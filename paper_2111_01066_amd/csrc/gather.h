@@ -1,6 +1,7 @@
-// Address-ordered gathers of a 128-row x 16-k chunk of an operand stored in
-// an arbitrary bit layout (internal): shared by the skewed matrix-core
-// kernels and the complex GEMM that reads its large operand in place.
+// Address-ordered gathers of a 128-row x 16-k (or 32-k) chunk of an
+// operand stored in an arbitrary bit layout (internal): shared by the skewed
+// matrix-core kernels and the complex GEMMs that read their large operand in
+// place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,7 +10,7 @@
 
 namespace tnrcs {
 
-constexpr int kSkewMaxV = 11;  // index bits of one chunk: 7 row bits + up to 4 k bits
+constexpr int kSkewMaxV = 12;  // index bits of one chunk: 7 row bits + up to 5 k bits
 
 // Address order of one chunk: chunk element e (0 .. 2^v) has its bit i at
 // A position pos[i], and is row bit mb[i] (or -1) / k bit kb[i] (or -1) of
@@ -24,14 +25,14 @@ struct SkewMap {
   int8_t pos[kSkewMaxV];
   int8_t mb[kSkewMaxV];
   int8_t kb[kSkewMaxV];
-  int8_t hk[4];
+  int8_t hk[5];
   int8_t hm[2];
 };
 
 __device__ __forceinline__ int skew_h(const SkewMap& mp, int m, int k) {
   int h = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 5; ++i)
     if ((k >> i) & 1) h ^= mp.hk[i];
 #pragma unroll
   for (int j = 0; j < 2; ++j)

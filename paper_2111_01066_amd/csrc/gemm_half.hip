@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "elem.h"
+#include "gather.h"
 #include "kernels.h"
 
 namespace tnrcs {
@@ -369,6 +370,218 @@ __global__ __launch_bounds__(512, 1) void k_hgemm_pp(const E* __restrict__ A, co
         if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
       }
   if (!to_work) record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
+}
+
+// A read in place (4M, 128x128 tiles, stages of 32 k, two waves per SIMD):
+// the stage's 128 x 32 A entries are gathered through the chunk map in A's
+// address order, four consecutive addresses per 16-byte load.  Those four
+// entries differ in A's two lowest index bits, which are the lowest row or
+// k bits; MODE says which (0: k0 k1, four k of one row; 1: k0 then row 0;
+// 2: row 0 then k0; 3: row 0 row 1, four rows at one k), and so how they are
+// deinterleaved into the planar [row][k] LDS rows.  The stage's K offset
+// moves by a carrying add restricted to A's K bits above 4 (in increasing
+// positions).  B is [N][K] and C is [M][N], as in k_hgemm.
+struct GatherAH {
+  SkewMap mp;
+  Runs aM;
+  uint64_t maskK = 0, incK = 0;
+};
+
+template <int MODE, typename H, typename E>
+__global__ __launch_bounds__(256, 2) void k_hgemm_ga(const E* __restrict__ A, const E* __restrict__ B,
+                                                   E* __restrict__ C, int64_t N, int64_t K, float out_scale,
+                                                   float* maxslot, int64_t Mt, int64_t Nt, const GatherAH g) {
+  typedef typename Frag<H>::T F;
+  constexpr int BK = 32, BM = 128, BN = 128, LDK = BK + 8, P = 2, WTM = 2, WTN = 2;
+  constexpr int NVB = BK / (256 / BN) / 4;  // B: uint4 loads per thread per stage
+  __shared__ __attribute__((aligned(16))) H As[2][P][BM][LDK];
+  __shared__ __attribute__((aligned(16))) H Bs[2][P][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t tm, tn, z;
+  xcd_tile(blockIdx.x, Mt, Nt, gridDim.x, tm, tn, z);
+  const int64_t bm = tm * BM, bn = tn * BN;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  floatx16 acc[P][WTM][WTN];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) acc[p][i][j] = floatx16{};
+  // this thread's four loads of a stage: offset of the first entry from the
+  // stage's first entry, and the LDS index (row * LDK + k) of that entry
+  uint32_t eoff[4];
+  int lidx[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint64_t off;
+    int m, k;
+    skew_split(g.mp, (j * 256 + tid) * 4, off, m, k);
+    eoff[j] = (uint32_t)off;
+    lidx[j] = m * LDK + k;
+  }
+  const uint64_t abase = dep((uint64_t)bm, g.aM);
+  uint64_t kofs = 0;
+  const int brow = tid / 2, bk = (tid % 2) * 16;
+  const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + brow) * K + bk);
+  uint4 ra[4], rb[NVB];
+  auto load_a = [&]() {
+    const E* base = A + (abase + kofs);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ra[j] = *reinterpret_cast<const uint4*>(base + eoff[j]);
+  };
+  auto store_a = [&](H (*S)[BM][LDK]) {
+    H* re = &S[0][0][0];
+    H* im = &S[1][0][0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t w[4] = {ra[j].x, ra[j].y, ra[j].z, ra[j].w};
+      const int i0 = lidx[j];
+      if constexpr (MODE == 0) {  // k, k+1, k+2, k+3 of one row
+        *reinterpret_cast<uint2*>(re + i0) = make_uint2(__builtin_amdgcn_perm(w[1], w[0], 0x05040100u),
+                                                        __builtin_amdgcn_perm(w[3], w[2], 0x05040100u));
+        *reinterpret_cast<uint2*>(im + i0) = make_uint2(__builtin_amdgcn_perm(w[1], w[0], 0x07060302u),
+                                                        __builtin_amdgcn_perm(w[3], w[2], 0x07060302u));
+      } else if constexpr (MODE == 1) {  // (m, k), (m, k+1), (m+1, k), (m+1, k+1)
+        *reinterpret_cast<uint32_t*>(re + i0) = __builtin_amdgcn_perm(w[1], w[0], 0x05040100u);
+        *reinterpret_cast<uint32_t*>(im + i0) = __builtin_amdgcn_perm(w[1], w[0], 0x07060302u);
+        *reinterpret_cast<uint32_t*>(re + i0 + LDK) = __builtin_amdgcn_perm(w[3], w[2], 0x05040100u);
+        *reinterpret_cast<uint32_t*>(im + i0 + LDK) = __builtin_amdgcn_perm(w[3], w[2], 0x07060302u);
+      } else if constexpr (MODE == 2) {  // (m, k), (m+1, k), (m, k+1), (m+1, k+1)
+        *reinterpret_cast<uint32_t*>(re + i0) = __builtin_amdgcn_perm(w[2], w[0], 0x05040100u);
+        *reinterpret_cast<uint32_t*>(im + i0) = __builtin_amdgcn_perm(w[2], w[0], 0x07060302u);
+        *reinterpret_cast<uint32_t*>(re + i0 + LDK) = __builtin_amdgcn_perm(w[3], w[1], 0x05040100u);
+        *reinterpret_cast<uint32_t*>(im + i0 + LDK) = __builtin_amdgcn_perm(w[3], w[1], 0x07060302u);
+      } else {  // rows m .. m+3 at one k
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          re[i0 + q * LDK] = __builtin_bit_cast(H, (uint16_t)(w[q] & 0xFFFFu));
+          im[i0 + q * LDK] = __builtin_bit_cast(H, (uint16_t)(w[q] >> 16));
+        }
+      }
+    }
+  };
+  auto load_b = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NVB; ++j) rb[j] = Bp[k0 / 4 + j];
+  };
+  load_a();
+  load_b(0);
+  store_a(As[0]);
+  store_stage<P, BN, LDK, NVB, H>(Bs[0], rb, brow, bk);
+  if (BK < K) {
+    kofs = ((kofs | ~g.maskK) + g.incK) & g.maskK;
+    load_a();
+    load_b(BK);
+  }
+  __syncthreads();
+  const int c = lane & 31, kq = (lane >> 5) * 8;
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      F a[P][WTM], b[P][WTN];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) a[p][i] = *reinterpret_cast<const F*>(&As[cur][p][wm + 32 * i + c][kk + kq]);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) b[p][j] = *reinterpret_cast<const F*>(&Bs[cur][p][wn + 32 * j + c][kk + kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          acc[0][i][j] = Frag<H>::mfma(a[0][i], b[0][j], acc[0][i][j]);
+          acc[1][i][j] = Frag<H>::mfma(a[0][i], b[1][j], acc[1][i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < WTM; ++i) {
+        uint4 t = __builtin_bit_cast(uint4, a[1][i]);
+        t.x ^= 0x80008000u;
+        t.y ^= 0x80008000u;
+        t.z ^= 0x80008000u;
+        t.w ^= 0x80008000u;
+        const F na = __builtin_bit_cast(F, t);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          acc[0][i][j] = Frag<H>::mfma(na, b[1][j], acc[0][i][j]);
+          acc[1][i][j] = Frag<H>::mfma(a[1][i], b[0][j], acc[1][i][j]);
+        }
+      }
+    }
+    if (k0 + BK < K) {
+      store_a(As[cur ^ 1]);
+      store_stage<P, BN, LDK, NVB, H>(Bs[cur ^ 1], rb, brow, bk);
+      if (k0 + 2 * BK < K) {
+        kofs = ((kofs | ~g.maskK) + g.incK) & g.maskK;
+        load_a();
+        load_b(k0 + 2 * BK);
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  float mx = 0.f;
+  const int kh = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int col = wn + 32 * j + c;
+        const float re = acc[0][i][j][r], im = acc[1][i][j][r];
+        mx = mag_max(mx, re, im);
+        C[(bm + row) * N + bn + col] = from_f2<E>(re * out_scale, im * out_scale);
+        if ((r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+  record_max_in(maxslot, mx, reinterpret_cast<float*>(&As[0][0][0][0]));
+}
+
+static uint64_t dep_host_h(uint64_t x, const Runs& r) {
+  uint64_t o = 0;
+  for (int i = 0; i < r.n; ++i) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
+  return o;
+}
+
+template <int MODE, typename H, typename E>
+static void hgemm_ga_launch(const E* A, const E* B, E* C, int64_t M, int64_t N, int64_t K, float scale,
+                            float* maxslot, const GatherAH& g, hipStream_t s) {
+  const int64_t Mt = M / 128, Nt = N / 128;
+  hipLaunchKernelGGL((k_hgemm_ga<MODE, H, E>), dim3((unsigned)(Mt * Nt)), dim3(256), 0, s, A, B, C, N, K, scale,
+                     maxslot, Mt, Nt, g);
+}
+
+template <typename H, typename E>
+static hipError_t hgemm_ga_t(const E* A, const E* B, E* C, const IndexOp& idx, float scale, float* maxslot,
+                             hipStream_t s) {
+  const int64_t M = (int64_t)1 << idx.nM, N = (int64_t)1 << idx.nN, K = (int64_t)1 << idx.nK;
+  GatherAH g{};
+  if (!skew_map(idx, 5, 0, &g.mp) || g.mp.v != 12) return hipErrorInvalidValue;
+  g.aM = idx.aM;
+  g.maskK = dep_host_h((uint64_t)(K - 1) & ~(uint64_t)31, idx.aK);
+  g.incK = K > 32 ? dep_host_h(32, idx.aK) : 0;
+  // the two lowest chunk bits are A's positions 0 and 1
+  if (g.mp.pos[0] != 0 || g.mp.pos[1] != 1) return hipErrorInvalidValue;
+  const bool k0 = g.mp.kb[0] == 0, k1 = g.mp.kb[1] == 1, m0 = g.mp.mb[0] == 0, m1 = g.mp.mb[1] == 1;
+  if (k0 && k1) hgemm_ga_launch<0, H, E>(A, B, C, M, N, K, scale, maxslot, g, s);
+  else if (k0 && g.mp.mb[1] == 0) hgemm_ga_launch<1, H, E>(A, B, C, M, N, K, scale, maxslot, g, s);
+  else if (m0 && g.mp.kb[1] == 0) hgemm_ga_launch<2, H, E>(A, B, C, M, N, K, scale, maxslot, g, s);
+  else if (m0 && m1) hgemm_ga_launch<3, H, E>(A, B, C, M, N, K, scale, maxslot, g, s);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_half_ga(int dtype, const void* A, const void* B, void* C, const IndexOp& idx, float out_scale,
+                               float* maxslot, hipStream_t s) {
+  if (!gemm_gather_ok(idx) || idx.nK < 5) return hipErrorInvalidValue;
+  if (dtype == TN_DTYPE_F16S)
+    return hgemm_ga_t<_Float16, cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, idx, out_scale, maxslot, s);
+  if (dtype == TN_DTYPE_BF16S)
+    return hgemm_ga_t<__bf16, cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, idx, out_scale, maxslot, s);
+  return hipErrorInvalidValue;
 }
 
 // C[i] = (sum over slabs s, in order, of W[s][i]) * scale, rounded to E.

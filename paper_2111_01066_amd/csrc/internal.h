@@ -57,7 +57,7 @@ struct GemmOp {
   int32_t tile = 0;       // workgroup tile edge: 0 = chosen by shape, 64 or 128 (autotuner)
   int32_t split_max = 1;  // split-K workspace capacity in slabs
   int32_t occ = 0;        // FP16/BF16 128x128 kernel: waves per SIMD (0 = chosen by K, 1 or 2; autotuner)
-  int32_t gather_a = 0;   // 1: A is read in its stored layout through the op's idx.aM / idx.aK (complex64)
+  int32_t gather_a = 0;   // 1: A is read in its stored layout through the op's idx.aM / idx.aK
 };
 
 // Generic / skinny: C[m, n] = sum_k A[dep(m,aM) | dep(k,aK)] * B[dep(n,bN) | dep(k,bK)],
@@ -205,12 +205,14 @@ inline unsigned step_classes(int nM, int nN, int nK) {
 }
 // The planner's rule among them: dense where valid and the contraction is
 // long (K >= 128) or the output wide (N >= 128), split-K for long sums into
-// few outputs, then the matrix-core skewed kernel, then the vector one, then
-// gathered.
+// few outputs, the vector skewed kernel for at most 2^4 terms x outputs,
+// then the matrix-core skewed kernel, then the vector one, then gathered.
 inline int default_class(int nM, int nN, int nK) {
   const unsigned m = step_classes(nM, nN, nK);
   if ((m & (1u << kOpGemm)) && (nK >= 7 || nN >= 7 || !(m & (1u << kOpSkew)))) return kOpGemm;
   if ((m & (1u << kOpSplitK)) && nK >= 10) return kOpSplitK;
+  // the fewest terms and outputs (a gate on a state): the vector-unit kernel
+  if ((m & (1u << kOpSkinny)) && nK + nN <= 4) return kOpSkinny;
   if (m & (1u << kOpSkew)) return kOpSkew;
   if (m & (1u << kOpSkinny)) return kOpSkinny;
   return kOpGeneric;
@@ -221,12 +223,14 @@ inline int run_pos(const Runs& r, int j) {
     if (j >= r.src[i] && j < r.src[i] + r.len[i]) return r.dst[i] + (j - r.src[i]);
   return -1;
 }
-// Complex64 GEMM steps whose large operand A (at least 2^kGatherMinLog2
+// GEMM steps whose large operand A (at least 2^kGatherMinLog2
 // entries) is not stored as [M bits, K bits] and whose sum has at least
 // 2^kGatherMinK terms read A in place instead of permuting it first, when
 // its layout admits that: 128 x 128 output tiles and chunks of 16 k (nM, nN
 // >= 7, nK >= 4), the chunk's 11 bits within A's low 32 positions, and the k
-// bits above 3 in increasing positions.
+// bits above 3 in increasing positions.  (The planner also requires at least
+// 512 output tiles when the sum has 2^11 terms or more, since the in-place
+// kernels do not split K.)
 constexpr int kGatherMinLog2 = 20;
 constexpr int kGatherMinK = 7;
 inline bool gemm_gather_ok(const IndexOp& idx) {

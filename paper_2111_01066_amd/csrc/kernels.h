@@ -39,6 +39,10 @@ hipError_t launch_gemm_c64(const float2* A, const float2* B, float2* C, int64_t 
 // alternative to permuting A first (gemm_gather_ok must hold).
 hipError_t launch_gemm_c64_ga(const float2* A, const float2* B, float2* C, const IndexOp& idx, int form,
                               hipStream_t s);
+// the same for scaled FP16/BF16 (4M, 128x128 tiles, stages of 32 k; nK >= 5):
+// C = A B^T * out_scale, max |A B^T| recorded in *maxslot
+hipError_t launch_gemm_half_ga(int dtype, const void* A, const void* B, void* C, const IndexOp& idx, float out_scale,
+                               float* maxslot, hipStream_t s);
 // scaled FP16/BF16 GEMM on half MFMA; C = A B^T * out_scale; max |A B^T| recorded in *maxslot.
 // tile: 0 auto, 64 or 128; occ (128 tiles): 0 auto, 1 or 2 waves per SIMD, 3 the
 // ping-pong 256x128 kernel (4M, M % 256 == 0, K per split % 32 == 0).

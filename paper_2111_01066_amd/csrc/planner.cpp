@@ -641,16 +641,21 @@ int build_plan(PlanCore& P, std::string& err) {
       };
       std::vector<int> Kord;
       if (!k_low_block(La, Kord) && !k_low_block(Lb, Kord)) Kord = K;
-      // complex64: a large A that would need a permute is read in place by
-      // the GEMM, with the K bits in A's own order (B is permuted to match).
-      // Only for K >= 128: on shorter sums the in-place GEMM (128x128 tiles
-      // only) measured slower than the permute plus the tuned GEMM.
+      // a large A that would need a permute is read in place by the GEMM,
+      // with the K bits in A's own order (B is permuted to match).  Only for
+      // K >= 128: on shorter sums the in-place GEMM (128x128 tiles only)
+      // measured slower than the permute plus the tuned GEMM.  Scaled
+      // storage uses the 4M form there.
       IndexOp gidx;
       bool gather = false;
       {
         std::vector<int> wa = MA;
         wa.insert(wa.end(), Kord.begin(), Kord.end());
-        if (!half && wa != La && ra >= kGatherMinLog2 && nK >= kGatherMinK) {
+        // the in-place kernels have no K split: a long sum needs enough
+        // 128x128 output tiles (512, two per CU) on its own
+        const bool fills = nM + nN - 14 >= 9 || nK < 11;
+        if (wa != La && ra >= kGatherMinLog2 && nK >= kGatherMinK && fills &&
+            (!half || P.opts.gemm_form != TN_GEMM_3M)) {
           gidx.nM = nM;
           gidx.nN = nN;
           gidx.nK = nK;

@@ -575,7 +575,7 @@ bool skew_map(const IndexOp& op, int kcb, int lv, SkewMap* mp) {
   // swizzle: a half-wave's store instruction covers chunk bits lv .. lv+4;
   // row bits 0..4 among them are bank bits already, the others (k bits, row
   // bits 5 and 6) are sent to the bank bits left free
-  for (int i = 0; i < 4; ++i) mp->hk[i] = 0;
+  for (int i = 0; i < 5; ++i) mp->hk[i] = 0;
   mp->hm[0] = mp->hm[1] = 0;
   unsigned used = 0;
   for (int i = lv; i < std::min(mp->v, lv + 5); ++i)

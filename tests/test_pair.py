@@ -68,9 +68,10 @@ TILED = [
 ALIGN = [([20, 21, 22] + list(range(12)), [30, 31, 32] + [5, 0, 9, 2, 11, 7, 1, 4, 10, 3, 8, 6],
           [20, 21, 22, 30, 31, 32])]
 # dense with an A of 2^20+ entries whose contracted wires are not its lowest
-# block and at least 128 terms: in complex64 the GEMM reads A in place (no
-# permute of A); K interleaved with M, K above M, and K split around M in
-# scattered order
+# block and at least 128 terms: the GEMM reads A in place (no permute of A);
+# K interleaved with M, K above M, K split around M in scattered order; A's
+# two lowest wires are (row, k), (row, row), (k, k) and (k, row), the four
+# ways the 16-bit kernel deinterleaves a 16-byte load
 GATHER = [
     ([600, 0, 601, 602, 1, 603, 2, 604, 605, 3, 606, 607, 4, 608, 609, 5, 610, 611, 6, 612],
      list(range(700, 707)) + [3, 1, 0, 2, 6, 5, 4], list(range(600, 613)) + list(range(700, 707))),
@@ -80,6 +81,8 @@ GATHER = [
      list(range(620, 634)) + list(range(720, 727))),
     ([8, 0] + list(range(640, 652)) + [7, 1, 6, 2, 5, 3, 4],
      list(range(740, 748)) + [4, 3, 5, 2, 6, 1, 7, 0, 8], list(range(640, 652)) + list(range(740, 748))),
+    ([0, 1, 2, 3, 4] + list(range(660, 673)) + [5, 673, 6], [6, 5, 4, 3, 2, 1, 0] + list(range(760, 767)),
+     list(range(660, 674)) + list(range(760, 767))),
 ]
 # long sums into more than 64 outputs: split-K over groups of 64 outputs
 # (512 and 2048 outputs; one operand's contracted wires scattered), and a
@@ -162,8 +165,11 @@ def test_pair_gather_cases_read_a_in_place(la, lb, lc):
     assert len(g) == 1 and g[0]["ga"] == 1 and g[0]["a"] == [3, 0]  # the caller's A, not a permuted copy
     assert all(o["a"] != [3, 0] for o in ops if o["kind"] == 0)
     pp.close()
-    # scaled storage keeps the permute of A
     pp = tnrcs.PairPlan(la, lb, lc, dry_run=True, dtype="f16s")
+    assert [o["ga"] for o in pp.json()["ops"] if o["kind"] == 1] == [1]
+    pp.close()
+    # the 16-bit in-place kernel is 4M only: a forced 3M form permutes A
+    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True, dtype="f16s", gemm_form="3m")
     assert all(o.get("ga", 0) == 0 for o in pp.json()["ops"])
     pp.close()
 

@@ -226,6 +226,8 @@ def _default_class(st):
         return 1
     if 4 in v and nK >= 10:
         return 4
+    if 3 in v and nK + nN <= 4:
+        return 3
     for k in (5, 3):
         if k in v:
             return k
