@@ -455,12 +455,15 @@ def oracle_timings(tnrcs, torch, np, c2_kernels):
     return out
 
 
-def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
+def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None, lanes: int = 4):
     """Config 5: the frozen uneven circuits whose order costs at most `cap`
     flops over all slices, one 64-amplitude bunch each, scaled storage,
-    autotuned GEMMs, one shared arena.  Times every plan's slices launched
-    plan by plan (each plan replaying its own per-slice graph) against the
-    same work as one batch graph launch; the two must agree bitwise."""
+    autotuned plans, `lanes` arena workspaces dealt round-robin (plans on
+    different workspaces may run side by side).  Times every plan's slices
+    launched plan by plan on one stream (each plan replaying its own
+    per-slice graph), plan by plan on one stream per workspace, and the same
+    work as one batch graph launch (one branch per workspace); all must
+    agree bitwise."""
     from rqcgen.workloads import config5, config5_table
     t = config5_table()
     wl = config5(max_total_flops=cap, table=t)
@@ -470,11 +473,11 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
         dry = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, dry_run=True, tune=True)
         need = max(need, dry.info()["arena_bytes"])
         dry.close()
-    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    arenas = [torch.empty(need, dtype=torch.uint8, device="cuda") for _ in range(lanes)]
     plans = []
     for i, w in enumerate(wl):
-        plans.append(tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype, arena=arena,
-                                tune=True, tune_db=tune_db))
+        plans.append(tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits, dtype=dtype,
+                                arena=arenas[i % lanes], tune=True, tune_db=tune_db))
         if (i + 1) % 32 == 0 or i + 1 == len(wl):
             log(f"[bench] batch: {i + 1}/{len(wl)} circuits planned, tuned and calibrated "
                 f"({time.perf_counter() - t0:.1f} s)")
@@ -503,6 +506,23 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
     torch.cuda.synchronize()
     t_seq = ev0.elapsed_time(ev1) / 1e3
     log(f"[bench] batch: plan-by-plan launches {t_seq:.3f} s ({flops / t_seq / 1e12:.1f} complex TFLOP/s)")
+    streams = [torch.cuda.Stream() for _ in range(lanes)]  # default priority
+    amps_ml = torch.zeros_like(amps_seq)
+
+    def multi_stream():
+        for i, p in enumerate(plans):
+            p.contract(0, n_sl[i], amps_ml[i], stream=streams[i % lanes])
+
+    multi_stream()
+    torch.cuda.synchronize()
+    amps_ml.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    multi_stream()
+    torch.cuda.synchronize()
+    t_ml = time.perf_counter() - t0
+    log(f"[bench] batch: plan-by-plan on {lanes} streams {t_ml:.3f} s ({flops / t_ml / 1e12:.1f} complex TFLOP/s), "
+        f"identical: {bool(torch.equal(amps_ml, amps_seq))}")
     t0 = time.perf_counter()
     b = tnrcs.Batch(plans, [(0, n) for n in n_sl], [amps_b[i] for i in range(len(plans))])
     t_build = time.perf_counter() - t0
@@ -539,9 +559,10 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None):
         f"{small:.3f} s of it in kernels with fewer than 2^20 outputs")
     for p in plans:
         p.close()
-    del arena
+    del arenas
     torch.cuda.empty_cache()
     return {"circuits": len(plans), "of": int(len(t["S"])), "max_order_flops": cap, "dtype": dtype,
+            "workspaces": lanes, "plan_by_plan_streams_s": t_ml,
             "kernel_time_s": busy, "kernel_time_over_one_graph": busy / t_b, "small_kernel_time_s": small,
             "time_to_amplitudes_with_plan_s": t_plan + t_b,
             "slices": int(sum(n_sl)), "kernels": kernels, "flops": flops, "arena_bytes": int(need),

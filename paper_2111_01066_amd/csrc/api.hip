@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -109,14 +110,45 @@ struct tn_plan_s {
   char* ext_c = nullptr;
 };
 
+// Independent lanes of a batch (plans on separate arenas); at most this
+// many run side by side.
+constexpr int kBatchMaxLanes = 4;
+
+// One captured graph per lane.  A run launches each lane's graph on a lane
+// stream of the batch, between a fork event recorded on the caller's stream
+// and join events the caller's stream waits for.  (One graph with a branch
+// per lane measured no faster than the lanes in sequence: its branches did
+// not overlap.)
 struct tn_batch_s {
   int device = 0;
   int64_t nodes = 0;
   std::vector<tn_plan_s*> plans;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
+  std::vector<hipStream_t> lane_streams;  // lane k >= 1 (lane 0 runs on the caller's stream)
+  std::vector<hipEvent_t> fork, join;     // fork[k] / join[k] for lane k >= 1
 };
+
+static void batch_release(tn_batch_s* b) {
+  for (hipGraphExec_t x : b->execs)
+    if (x) hipGraphExecDestroy(x);
+  for (hipGraph_t g : b->graphs)
+    if (g) hipGraphDestroy(g);
+  for (hipStream_t st : b->lane_streams)
+    if (st) hipStreamDestroy(st);
+  for (hipEvent_t ev : b->fork)
+    if (ev) hipEventDestroy(ev);
+  for (hipEvent_t ev : b->join)
+    if (ev) hipEventDestroy(ev);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  b->execs.clear();
+  b->graphs.clear();
+  b->lane_streams.clear();
+  b->fork.clear();
+  b->join.clear();
+  b->cap_stream = nullptr;
+}
 
 static char* resolve(const tn_plan_s* p, const TRef& r) {
   char* base;
@@ -921,39 +953,80 @@ int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, vo
     return TN_OK;
   }
   auto bail = [&](int code) {
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    batch_release(b);
     delete b;
     return code;
   };
+  // lanes: plans whose arenas overlap (or that share a plan or an output
+  // buffer) run one after another in one lane; different lanes are
+  // independent and may run side by side
+  std::vector<int> lane(n);
+  for (int i = 0; i < n; ++i) lane[i] = i;
+  std::function<int(int)> root = [&](int i) { return lane[i] == i ? i : (lane[i] = root(lane[i])); };
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const tn_plan_s *p = plans[i], *q = plans[j];
+      const char *pa = p->d_arena, *qa = q->d_arena;
+      const int64_t pn = p->core.arena_elems * p->eb, qn = q->core.arena_elems * q->eb;
+      const bool overlap = pn > 0 && qn > 0 && pa < qa + qn && qa < pa + pn;
+      if (overlap || p == q || amps[i] == amps[j]) lane[root(i)] = root(j);
+    }
+  std::vector<int> lane_of(n), first_of;  // dense lane ids in order of first appearance
+  for (int i = 0; i < n; ++i) {
+    const int r = root(i);
+    int id = -1;
+    for (size_t k = 0; k < first_of.size(); ++k)
+      if (first_of[k] == r) id = (int)k;
+    if (id < 0) {
+      id = (int)first_of.size();
+      first_of.push_back(r);
+    }
+    lane_of[i] = id;
+  }
+  const int n_lanes = std::max<int>(1, std::min<int>((int)first_of.size(), kBatchMaxLanes));
+  for (int i = 0; i < n; ++i) lane_of[i] %= n_lanes;
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
   if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     return bail(hip_fail(e, "create capture stream"));
-  if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-    return bail(hip_fail(e, "begin capture"));
-  int rc = TN_OK;
-  for (int i = 0; i < n && rc == TN_OK; ++i) {
-    tn_plan_s* p = plans[i];
-    const int64_t s0 = ranges[2 * i], s1 = ranges[2 * i + 1];
-    if (s1 == s0) continue;
-    hipError_t e2 = launch_set_ctrl(p->d_ctrl, s0, amps[i], b->cap_stream);
-    if (e2 != hipSuccess) rc = hip_fail(e2, "control kernel");
-    for (int64_t sl = s0; sl < s1 && rc == TN_OK; ++sl) rc = enqueue_slice(p, b->cap_stream);
-  }
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(b->cap_stream, &g);
-  if (rc) {
-    if (g) hipGraphDestroy(g);
-    return bail(rc);
-  }
-  if (e != hipSuccess) return bail(hip_fail(e, "end capture"));
-  b->graph = g;
-  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
-    hipGraphDestroy(b->graph);
-    return bail(hip_fail(e, "instantiate batch graph"));
+  for (int k = 0; k < n_lanes; ++k) {
+    std::vector<int> mine;
+    for (int i = 0; i < n; ++i)
+      if (lane_of[i] == k && ranges[2 * i + 1] > ranges[2 * i]) mine.push_back(i);
+    if (mine.empty()) continue;
+    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return bail(hip_fail(e, "begin capture"));
+    int rc = TN_OK;
+    for (int i : mine) {
+      if (rc) break;
+      tn_plan_s* p = plans[i];
+      const int64_t s0 = ranges[2 * i], s1 = ranges[2 * i + 1];
+      hipError_t e2 = launch_set_ctrl(p->d_ctrl, s0, amps[i], b->cap_stream);
+      if (e2 != hipSuccess) rc = hip_fail(e2, "control kernel");
+      for (int64_t sl = s0; sl < s1 && rc == TN_OK; ++sl) rc = enqueue_slice(p, b->cap_stream);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (g) b->graphs.push_back(g);
+    if (rc) return bail(rc);
+    if (e != hipSuccess) return bail(hip_fail(e, "end capture"));
+    hipGraphExec_t x = nullptr;
+    if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
+      return bail(hip_fail(e, "instantiate batch graph"));
+    b->execs.push_back(x);
   }
   hipStreamDestroy(b->cap_stream);
   b->cap_stream = nullptr;
+  for (size_t k = 1; k < b->execs.size(); ++k) {
+    hipStream_t st = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) == hipSuccess) b->lane_streams.push_back(st);
+    if (e == hipSuccess && (e = hipEventCreateWithFlags(&f, hipEventDisableTiming)) == hipSuccess)
+      b->fork.push_back(f);
+    if (e == hipSuccess && (e = hipEventCreateWithFlags(&j, hipEventDisableTiming)) == hipSuccess)
+      b->join.push_back(j);
+    if (e != hipSuccess) return bail(hip_fail(e, "create lane stream"));
+  }
   *out = b;
   return TN_OK;
 }
@@ -965,17 +1038,25 @@ int tn_batch_run(tn_batch_t b, void* stream) {
     p->last_stream = s;
     p->ran = true;
   }
-  if (!b->exec) return TN_OK;
+  if (b->execs.empty()) return TN_OK;
   HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
-  HIP_TRY(hipGraphLaunch(b->exec, s), "batch graph launch");
+  // lanes 1.. start after the work already on the caller's stream, lane 0
+  // runs on it, and the caller's stream then waits for every lane
+  for (size_t k = 1; k < b->execs.size(); ++k) {
+    HIP_TRY(hipEventRecord(b->fork[k - 1], s), "batch fork");
+    HIP_TRY(hipStreamWaitEvent(b->lane_streams[k - 1], b->fork[k - 1], 0), "batch fork");
+    HIP_TRY(hipGraphLaunch(b->execs[k], b->lane_streams[k - 1]), "batch graph launch");
+    HIP_TRY(hipEventRecord(b->join[k - 1], b->lane_streams[k - 1]), "batch join");
+  }
+  HIP_TRY(hipGraphLaunch(b->execs[0], s), "batch graph launch");
+  for (size_t k = 1; k < b->execs.size(); ++k) HIP_TRY(hipStreamWaitEvent(s, b->join[k - 1], 0), "batch join");
   return TN_OK;
 }
 
 int tn_batch_destroy(tn_batch_t b) {
   if (!b) return TN_OK;
   hipSetDevice(b->device);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  batch_release(b);
   delete b;
   return TN_OK;
 }

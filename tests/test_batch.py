@@ -43,22 +43,26 @@ def small():
     return _small_batch()
 
 
-def _shared_plans(cases, dtype, tune=False, tune_db=None):
+def _shared_plans(cases, dtype, tune=False, tune_db=None, workspaces=1):
+    """Plans on `workspaces` arena workspaces, dealt round-robin (plans on
+    different workspaces go to different lanes of a batch graph)."""
     need = 0
     for c, open_q, bits, pairs, sliced, _ in cases:
         dry = tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, dry_run=True, tune=tune)
         need = max(need, dry.info()["arena_bytes"])
         dry.close()
-    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=DEV)
-    plans = [tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, arena=ws, tune=tune, tune_db=tune_db)
-             for c, open_q, bits, pairs, sliced, _ in cases]
+    ws = [torch.empty(max(need, 256), dtype=torch.uint8, device=DEV) for _ in range(workspaces)]
+    plans = [tnrcs.Plan(c, pairs, sliced, open_q, bits, dtype=dtype, arena=ws[i % workspaces], tune=tune,
+                        tune_db=tune_db)
+             for i, (c, open_q, bits, pairs, sliced, _) in enumerate(cases)]
     return plans, ws
 
 
+@pytest.mark.parametrize("workspaces", [1, 3])
 @pytest.mark.parametrize("dtype", ["c64", "f16s"])
-def test_batch_matches_per_plan_runs_and_oracle(small, dtype):
-    print(f"batch of {len(small)} small uneven circuits, {dtype}, shared arena", flush=True)
-    plans, ws = _shared_plans(small, dtype)
+def test_batch_matches_per_plan_runs_and_oracle(small, dtype, workspaces):
+    print(f"batch of {len(small)} small uneven circuits, {dtype}, {workspaces} arena workspace(s)", flush=True)
+    plans, ws = _shared_plans(small, dtype, workspaces=workspaces)
     n_sl = [p.info()["n_slices"] for p in plans]
     assert any(n > 1 for n in n_sl)
     seq = [torch.zeros(64, dtype=torch.complex128, device=DEV) for _ in plans]
