@@ -298,6 +298,37 @@ def micro(tnrcs, torch, np):
         log(f"[bench] skewed contraction (rank 30 x two-qubit gate) {dtype}: {gbs:.0f} GB/s ({gbs / PEAK_HBM:.1%})")
         pp.close()
         del A, B, C
+    # skewed contraction with a large B (Fig. S7b's case): 2^22 rows of A
+    # whose 2^9 contracted entries are interleaved with the row bits, against
+    # B of 32 x 2^9 entries (staged through LDS chunk by chunk), as in the
+    # 53-qubit network's largest-K skewed step
+    la = [1000 + i for i in range(22)]
+    kk = list(range(9))
+    la = la[:6] + kk[:3] + la[6:14] + kk[3:6] + la[14:] + kk[6:]
+    lb = [2000 + j for j in range(5)] + kk[::-1]
+    lc = [1000 + i for i in range(22)] + [2000 + j for j in range(5)]
+    for dtype in ("c64", "f16s"):
+        pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
+        kinds = [o["kind"] for o in pp.json()["ops"]]
+        eb = 8 if dtype == "c64" else 4
+        if dtype == "c64":
+            A = torch.ones(1 << 31, dtype=torch.complex64, device="cuda")
+            B = torch.ones(1 << 14, dtype=torch.complex64, device="cuda")
+            C = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+        else:
+            A = torch.ones(1 << 31, 2, dtype=torch.float16, device="cuda")
+            B = torch.ones(1 << 14, 2, dtype=torch.float16, device="cuda")
+            C = torch.empty(1 << 27, 2, dtype=torch.float16, device="cuda")
+        ms = timed(lambda: pp.run(A, B, C, out_scale=1.0 if dtype == "c64" else 2.0 ** -9))
+        byts = eb * ((1 << 31) + (1 << 14) + (1 << 27))
+        gbs, tfl = byts / ms / 1e6, 8.0 * (1 << 22) * 32 * 512 / ms / 1e9
+        out[f"skew_large_b_{dtype}"] = {"GB/s": gbs, "frac_hbm": gbs / PEAK_HBM, "complex_tflops": tfl,
+                                        "kernels": kinds, "ms": ms}
+        log(f"[bench] skewed contraction with large B (2^22 x 32 outputs, K = 2^9) {dtype}: {ms:.2f} ms, "
+            f"{gbs:.0f} GB/s ({gbs / PEAK_HBM:.1%}), {tfl:.0f} complex TFLOP/s, kernels {kinds}")
+        pp.close()
+        del A, B, C
+    torch.cuda.empty_cache()
     # config 2: 32 pairs of rank-27 x rank-25 complex tensors sharing 12 indices
     from rqcgen.workloads import config2_pair
     la, lb, lc = config2_pair(seed=2)
