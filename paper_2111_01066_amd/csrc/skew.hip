@@ -554,6 +554,164 @@ __global__ __launch_bounds__(256, 2) void k_skew_ph(const E* __restrict__ A, con
 
 static size_t skew_ph_lds(int K, int np) { return 2 * kSkewPM * kSkewHS * 2 + 2 * np * (K + 8) * 2 + 64 * 8; }
 
+// Scaled FP16 / BF16 with a long sum (128 <= K <= 2^10): B does not stay
+// in LDS (Fig. S7b's case), so each 16-k chunk of B (2^nN x 16 entries,
+// re-read from L2 by every pass) is staged beside the chunk of A.  Chunks
+// run in a runtime loop, two per iteration so that each has its own
+// registers: the chunk two ahead is loaded while the current one is
+// multiplied.  The chunks' K offsets in A and B move by one XOR per chunk
+// with prefix tables (B's K bits need not keep their order).  Past the last
+// pass the loads repeat the last pass's chunks (read, never used).
+constexpr int kSkewBS = 24;  // LDS row stride of a staged B chunk (entries)
+
+template <int NT, int VEC, typename E>
+__global__ __launch_bounds__(256, 2) void k_skew_phc(const E* __restrict__ A, const E* __restrict__ B,
+                                                    E* __restrict__ C, const IndexOp op, const SkewMap mp,
+                                                    float* maxslot) {
+  typedef typename SkewHalf<E>::H H;
+  typedef typename SkewHalf<E>::V V;
+  constexpr int KC = 16, NP = 32 * NT;
+  constexpr int LPT = (kSkewPM * KC) / 256 / VEC;
+  constexpr int NBT = NP * KC / 256;  // B entries per thread per chunk
+  __shared__ __attribute__((aligned(16))) H As[2 * kSkewPM * kSkewHS];  // re, im planes [PM][HS]
+  __shared__ __attribute__((aligned(16))) H Bs[2 * NP * kSkewBS];       // re, im planes [NP][BS]
+  __shared__ uint64_t pre_a[12], pre_b[12];
+  __shared__ float red[16];
+  const int N = 1 << op.nN;
+  const int nch = 1 << (op.nK - 4);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 31, kh = lane >> 5;
+  // prefix tables: chunk ch -> ch + 1 flips the chunk-index bits 0 .. ctz(ch + 1)
+  if (tid < op.nK - 4) {
+    uint64_t xa = 0, xb = 0;
+    for (int j = 0; j <= tid; ++j) {
+      xa ^= dep((uint64_t)KC << j, op.aK);
+      xb ^= dep((uint64_t)KC << j, op.bK);
+    }
+    pre_a[tid] = xa;
+    pre_b[tid] = xb;
+  }
+  uint64_t eoff[LPT];
+  int eidx[LPT][VEC];  // LDS index m * kSkewHS + k of each A entry
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      uint64_t off;
+      int m, k;
+      skew_split(mp, (j * 256 + tid) * VEC + u, off, m, k);
+      if (u == 0) eoff[j] = off;
+      eidx[j][u] = m * kSkewHS + k;
+    }
+  }
+  uint64_t boff[NBT];
+  int bidx[NBT];
+  bool bval[NBT];
+#pragma unroll
+  for (int r = 0; r < NBT; ++r) {
+    const int i = r * 256 + tid, n = i / KC, k = i % KC;
+    bval[r] = n < N;
+    boff[r] = bval[r] ? (dep((uint64_t)n, op.bN) | dep((uint64_t)k, op.bK)) : 0;
+    bidx[r] = n * kSkewBS + k;
+  }
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const int64_t my_passes = passes > (int64_t)blockIdx.x ? (passes - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  const uint64_t mask_m = dep(((uint64_t)1 << op.nM) - kSkewPM, op.aM);
+  const uint64_t inc_m = dep((uint64_t)gridDim.x * kSkewPM, op.aM);
+  __syncthreads();
+  // the chunk being prefetched: its pass's row offset, chunk index and K offsets
+  uint64_t pf_m = dep((uint64_t)blockIdx.x * kSkewPM, op.aM), pf_ka = 0, pf_kb = 0;
+  int pf_ch = 0;
+  int64_t pf_left = my_passes;  // passes not yet fully prefetched
+  E v[2][LPT][VEC];
+  E w[2][NBT];
+  auto prefetch = [&](int d) {
+    const E* base = A + (pf_m | pf_ka);
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      if constexpr (VEC == 1) {
+        v[d][j][0] = skew_ld_nt(base + eoff[j]);
+      } else {
+        const skew_u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const skew_u32x4*>(base + eoff[j]));
+        __builtin_memcpy(&v[d][j][0], &x, 16);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NBT; ++r) w[d][r] = B[pf_kb | boff[r]];
+    if (++pf_ch == nch) {
+      pf_ch = 0;
+      pf_ka = pf_kb = 0;
+      if (pf_left > 1) pf_m = ((pf_m | ~mask_m) + inc_m) & mask_m;
+      --pf_left;
+    } else {
+      const int t = __builtin_ctz((unsigned)pf_ch);
+      pf_ka ^= pre_a[t];
+      pf_kb ^= pre_b[t];
+    }
+  };
+  prefetch(0);
+  prefetch(1);
+  const int arow = (wave * 32 + c) * kSkewHS + 8 * kh;
+  float mx = 0.f;
+  for (int64_t pi = 0; pi < my_passes; ++pi) {
+    const int64_t m0 = ((int64_t)blockIdx.x + pi * (int64_t)gridDim.x) * kSkewPM;
+    floatx16 acc[2][NT];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[q][j] = floatx16{};
+    for (int ch = 0; ch < nch; ch += 2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        __syncthreads();  // the previous chunk's products have read As and Bs
+#pragma unroll
+        for (int j = 0; j < LPT; ++j)
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            As[eidx[j][u]] = v[d][j][u].re;
+            As[kSkewPM * kSkewHS + eidx[j][u]] = v[d][j][u].im;
+          }
+#pragma unroll
+        for (int r = 0; r < NBT; ++r) {
+          const E x = bval[r] ? w[d][r] : E{};
+          Bs[bidx[r]] = x.re;
+          Bs[NP * kSkewBS + bidx[r]] = x.im;
+        }
+        prefetch(d);  // two chunks ahead
+        __syncthreads();
+        const V ar = *reinterpret_cast<const V*>(As + arow);
+        const V ai = *reinterpret_cast<const V*>(As + kSkewPM * kSkewHS + arow);
+        const V nai = -ai;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int brow = (32 * j + c) * kSkewBS + 8 * kh;
+          const V br = *reinterpret_cast<const V*>(Bs + brow);
+          const V bi = *reinterpret_cast<const V*>(Bs + NP * kSkewBS + brow);
+          acc[0][j] = SkewHalf<E>::mfma(ar, br, acc[0][j]);
+          acc[0][j] = SkewHalf<E>::mfma(nai, bi, acc[0][j]);
+          acc[1][j] = SkewHalf<E>::mfma(ar, bi, acc[1][j]);
+          acc[1][j] = SkewHalf<E>::mfma(ai, br, acc[1][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = 32 * j + c;
+      if (col < N) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+          const float cr = acc[0][j][r], ci = acc[1][j][r];
+          mx = mag_max(mx, cr, ci);
+          skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  record_max_in(maxslot, mx, red);
+}
+
 bool skew_ok(const IndexOp& op) { return op.nN <= 6 && op.nK >= 1 && op.nK <= 10 && op.nM >= 7; }
 
 bool skew_map(const IndexOp& op, int kcb, int lv, SkewMap* mp) {
@@ -726,12 +884,31 @@ static hipError_t launch_skew_h(const E* A, const E* B, E* C, const IndexOp& op,
   }
 }
 
+// 16-bit storage with 128 <= K <= 2^10: B staged chunk by chunk
+template <int NT, typename E>
+static hipError_t launch_skew_hc(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
+  constexpr int VEC = 16 / (int)sizeof(E);
+  SkewMap mp{};
+  if (!skew_map(op, 4, 2, &mp)) return hipErrorInvalidValue;
+  const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
+  const dim3 g((unsigned)std::min<int64_t>(passes, 512));
+  if (mp.pos[0] == 0 && mp.pos[1] == 1)
+    hipLaunchKernelGGL((k_skew_phc<NT, VEC, E>), g, dim3(256), 0, s, A, B, C, op, mp, maxslot);
+  else
+    hipLaunchKernelGGL((k_skew_phc<NT, 1, E>), g, dim3(256), 0, s, A, B, C, op, mp, maxslot);
+  return hipGetLastError();
+}
+
 template <typename E>
 static hipError_t launch_skew_e(const E* A, const E* B, E* C, const IndexOp& op, float* maxslot, hipStream_t s) {
   if constexpr (sizeof(E) == 4) {
     if (op.nK >= 4 && op.nK <= 6) {
       if (op.nN <= 5) return launch_skew_h<1, E>(A, B, C, op, maxslot, s);
       return launch_skew_h<2, E>(A, B, C, op, maxslot, s);
+    }
+    if (op.nK >= 7 && op.nK <= 10) {
+      if (op.nN <= 5) return launch_skew_hc<1, E>(A, B, C, op, maxslot, s);
+      return launch_skew_hc<2, E>(A, B, C, op, maxslot, s);
     }
   }
   if (op.nN <= 5) return launch_skew_t<1, E>(A, B, C, op, maxslot, s);
