@@ -253,7 +253,10 @@ __global__ __launch_bounds__(256, 2) void k_skew(const E* __restrict__ A, const 
 // passes; a chunk's slot is reloaded as soon as the chunk is in LDS, so
 // the loads spread over the pass); past the last pass the loads repeat the
 // last pass's chunks (read, never used).
-template <int NT, int VEC, int KC, int NCH, int PD, typename E>
+// STG: rows of at most 16 outputs (NT = 1): a pass's 128 x N outputs are one
+// contiguous range of C; they are staged in the (then idle) A chunk planes
+// and written in 16-byte runs instead of one 8- or 4-byte store per lane.
+template <int NT, int VEC, int KC, int NCH, int PD, int STG, typename E>
 __global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, const E* __restrict__ B,
                                                   E* __restrict__ C, const IndexOp op, const SkewMap mp,
                                                   float* maxslot) {
@@ -373,17 +376,38 @@ __global__ __launch_bounds__(256, 2) void k_skew_p(const E* __restrict__ A, cons
                                                              0, 0, 0);
           }
       }
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const int col = 32 * j + c;
-        if (col < N) {
+      if constexpr (STG) {
+        __syncthreads();  // every wave has multiplied the pass's last chunk
+        E* Cs = reinterpret_cast<E*>(As);
+        if (c < N) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-            const float cr = acc[0][j][r] - acc[1][j][r];
-            const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
+            const float cr = acc[0][0][r] - acc[1][0][r];
+            const float ci = acc[2][0][r] - acc[0][0][r] - acc[1][0][r];
             mx = mag_max(mx, cr, ci);
-            skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
+            Cs[row * N + c] = from_f2<E>(cr * op.out_scale, ci * op.out_scale);
+          }
+        }
+        __syncthreads();
+        constexpr int EPV = 16 / (int)sizeof(E);
+        E* Cp = C + (m0 << op.nN);
+        for (int i = tid * EPV; i < kSkewPM * N; i += 256 * EPV)
+          __builtin_nontemporal_store(*reinterpret_cast<const skew_u32x4*>(Cs + i),
+                                      reinterpret_cast<skew_u32x4*>(Cp + i));
+      } else {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int col = 32 * j + c;
+          if (col < N) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = wave * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+              const float cr = acc[0][j][r] - acc[1][j][r];
+              const float ci = acc[2][j][r] - acc[0][j][r] - acc[1][j][r];
+              mx = mag_max(mx, cr, ci);
+              skew_st_nt(C + (((m0 + row) << op.nN) | col), from_f2<E>(cr * op.out_scale, ci * op.out_scale));
+            }
           }
         }
       }
@@ -807,7 +831,14 @@ static hipError_t launch_skew_pass(const E* A, const E* B, E* C, const IndexOp& 
   const size_t lds = skew_p_lds(KC, KC * NCH, 32 * NT);
   const int64_t passes = ((int64_t)1 << op.nM) / kSkewPM;
   const dim3 g((unsigned)std::min<int64_t>(passes, 512));
-  hipLaunchKernelGGL((k_skew_p<NT, VEC, KC, NCH, PD, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot);
+  // staged output rows: at most 16 per row, fitting the A chunk planes
+  const bool stg = NT == 1 && op.nN <= 4 &&
+                   (size_t)kSkewPM * ((size_t)1 << op.nN) * sizeof(E) <= (size_t)2 * KC * kSkewLDA * sizeof(float) &&
+                   kSkewPM * ((int64_t)1 << op.nN) * (int64_t)sizeof(E) >= 16;
+  if (stg)
+    hipLaunchKernelGGL((k_skew_p<NT, VEC, KC, NCH, PD, 1, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot);
+  else
+    hipLaunchKernelGGL((k_skew_p<NT, VEC, KC, NCH, PD, 0, E>), g, dim3(256), lds, s, A, B, C, op, mp, maxslot);
   return hipGetLastError();
 }
 
