@@ -145,13 +145,16 @@ typedef struct {
  * is run in each on a one-step plan of the same operand layouts over
  * scratch buffers of random values (at most 48 GiB and a third of the free
  * device memory; larger steps keep the default rule; the gathered kernel is
- * timed only on steps of at most 2^22 outputs), and the fastest is
- * planned.  With the environment variable TNRCS_VERBOSE set, each tuned step
- * prints a line on stderr.  Tile:
- * for each distinct dense-GEMM shape of the plan (dtype, M, N, K, form)
- * every valid tile size, K-split count and kernel variant is timed with HIP
- * events on the plan's own buffers (the arena is filled with random values
- * first: the matrix cores run faster on zeros) and the fastest kept.
+ * timed only on steps of at most 2^22 outputs and sums shorter than 2^16
+ * terms), and the fastest is planned.  With the environment variable
+ * TNRCS_VERBOSE set, each tuned step prints a line on stderr.  Tile: for
+ * each distinct dense-GEMM shape of the plan (dtype, M, N, K, form) every
+ * valid tile size, K-split count and kernel variant is timed with HIP events
+ * on the plan's own buffers (the arena is filled with random values first:
+ * the matrix cores run faster on zeros) and the fastest kept.  Dense steps
+ * that read a large A in place (no permute of A; at least 2^7 terms and,
+ * for sums of 2^11 terms or more, at least 512 output tiles of 128x128)
+ * have one fixed kernel and are not timed.
  * Results are cached per process and, with tune_db, in a file (lines
  * "tnrcs-class dtype key class ms" and "tnrcs-gemm dtype M N K form cap tile
  * split occ ms"; the key is the step's operand and result layouts with the
