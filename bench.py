@@ -43,9 +43,13 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, dtype: str):
+def measured_traffic(kernel: str, dtype: str, alg_bytes_per_launch: float = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources (else None)."""
+    it was taken on the current kernel sources (else None).  The summary
+    holds, for the dominant kernel's launches of the profiled run, the HBM
+    bytes per launch and their ratio to the algorithmic bytes of the same
+    launches; a tuned plan may mix its launches differently from run to run,
+    so the ratio is applied to this run's algorithmic bytes per launch."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -53,7 +57,11 @@ def measured_traffic(kernel: str, dtype: str):
         d = json.load(f)
     if d.get("source_sha") != source_sha():
         return None
-    return d.get("per_launch_bytes", {}).get(f"{kernel}:{dtype}")
+    key = f"{kernel}:{dtype}"
+    ratio = d.get("hbm_over_algorithmic", {}).get(key)
+    if ratio is not None and alg_bytes_per_launch:
+        return ratio * alg_bytes_per_launch
+    return d.get("per_launch_bytes", {}).get(key)
 
 
 def w_flops_per_slice(w):
@@ -183,10 +191,13 @@ def roofline(by_kind, dtype, copy_gbs=None):
                         "per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain copy)"}
     achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
     r = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-         "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype), "launches_per_slice": d["n"],
+         "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype, d["bytes"] / d["n"]),
+         "launches_per_slice": d["n"],
          "avg_ms": avg_ms, "bytes_per_launch": d["bytes"] / d["n"],
          "note": "achieved = algorithmic bytes per launch (each operand read once, the output written once) / "
-                 "mean launch duration (HIP events on the launch stream)"}
+                 "mean launch duration (HIP events on the launch stream); traffic = this run's algorithmic bytes "
+                 "per launch x the HBM/algorithmic ratio that rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by a "
+                 "plain copy) measured on the same kernel (profiles/traffic.json)"}
     if copy_gbs:
         r["copy_probe_GB/s"] = copy_gbs
         r["frac_of_copy_probe"] = achieved / copy_gbs
