@@ -777,8 +777,12 @@ int build_plan(PlanCore& P, std::string& err) {
       // permuted to [free wires, K]
       int tmp[2] = {-1, -1};
       std::vector<int> lay2[2] = {La, Lb};
-      if (splitk) {
-        for (int side = 0; side < 2; ++side) {
+      // the matrix-core skewed kernel with a long sum stages B chunk by
+      // chunk: a B whose low k bits are scattered is permuted first too
+      // (B only; A is read in place)
+      const bool skew_long = cls == kOpSkew && nK >= 7;
+      if (splitk || skew_long) {
+        for (int side = skew_long ? 1 : 0; side < 2; ++side) {
           const std::vector<int>& have = side ? Lb : La;
           const int r = (int)have.size();
           bool aligned = true;
