@@ -226,6 +226,39 @@ def copy_ceiling(tnrcs, torch, gib: int = 8, reps: int = 5):
     return 2.0 * nb / sorted(ts)[reps // 2] / 1e6
 
 
+def config2_pairs(tnrcs, torch, timed, dtypes=("c64", "f16s")):
+    """Config 2: 32 pairs of rank-27 x rank-25 complex tensors sharing 12
+    indices, one pairwise-contraction launch (GEMM M = 2^15, N = 2^13,
+    K = 2^12 per pair, permutes included)."""
+    out = {}
+    from rqcgen.workloads import config2_pair
+    la, lb, lc = config2_pair(seed=2)
+    n_pairs = 32
+    for dtype in dtypes:
+        pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(2)
+        if dtype == "c64":
+            A = torch.randn(n_pairs, 1 << 27, dtype=torch.complex64, device="cuda", generator=g)
+            B = torch.randn(n_pairs, 1 << 25, dtype=torch.complex64, device="cuda", generator=g)
+            C = torch.empty(n_pairs, 1 << 28, dtype=torch.complex64, device="cuda")
+        else:
+            A = torch.randn(n_pairs, 1 << 27, 2, device="cuda", generator=g).half()
+            B = torch.randn(n_pairs, 1 << 25, 2, device="cuda", generator=g).half()
+            C = torch.empty(n_pairs, 1 << 28, 2, dtype=torch.float16, device="cuda")
+        ms = timed(lambda: pp.run(A, B, C, batch=n_pairs, out_scale=1.0 if dtype == "c64" else 2.0 ** -8), n=2)
+        fl = 8.0 * 2 ** 15 * 2 ** 13 * 2 ** 12 * n_pairs
+        tf = fl / ms / 1e9
+        out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
+                                          "complex_rate_over_dtype_mfma_peak": tf / PEAK[dtype]}
+        log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
+            f"TFLOP/s ({tf / PEAK[dtype]:.1%} of the {dtype} MFMA peak, permutes included)")
+        pp.close()
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def micro(tnrcs, torch, np):
     """Standalone kernels on the shapes that matter, timed with HIP events."""
     out = {}
@@ -340,32 +373,7 @@ def micro(tnrcs, torch, np):
         pp.close()
         del A, B, C
     torch.cuda.empty_cache()
-    # config 2: 32 pairs of rank-27 x rank-25 complex tensors sharing 12 indices
-    from rqcgen.workloads import config2_pair
-    la, lb, lc = config2_pair(seed=2)
-    n_pairs = 32
-    for dtype in ("c64", "f16s"):
-        pp = tnrcs.PairPlan(la, lb, lc, dtype=dtype)
-        g = torch.Generator(device="cuda")
-        g.manual_seed(2)
-        if dtype == "c64":
-            A = torch.randn(n_pairs, 1 << 27, dtype=torch.complex64, device="cuda", generator=g)
-            B = torch.randn(n_pairs, 1 << 25, dtype=torch.complex64, device="cuda", generator=g)
-            C = torch.empty(n_pairs, 1 << 28, dtype=torch.complex64, device="cuda")
-        else:
-            A = torch.randn(n_pairs, 1 << 27, 2, device="cuda", generator=g).half()
-            B = torch.randn(n_pairs, 1 << 25, 2, device="cuda", generator=g).half()
-            C = torch.empty(n_pairs, 1 << 28, 2, dtype=torch.float16, device="cuda")
-        ms = timed(lambda: pp.run(A, B, C, batch=n_pairs, out_scale=1.0 if dtype == "c64" else 2.0 ** -8), n=2)
-        fl = 8.0 * 2 ** 15 * 2 ** 13 * 2 ** 12 * n_pairs
-        tf = fl / ms / 1e9
-        out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
-                                          "complex_rate_over_dtype_mfma_peak": tf / PEAK[dtype]}
-        log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
-            f"TFLOP/s ({tf / PEAK[dtype]:.1%} of the {dtype} MFMA peak, permutes included)")
-        pp.close()
-        del A, B, C
-        torch.cuda.empty_cache()
+    out.update(config2_pairs(tnrcs, torch, timed))
     return out
 
 
@@ -632,6 +640,7 @@ def main():
                     help="config 5: keep the circuits whose frozen order costs at most this many flops")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched uneven workload")
     ap.add_argument("--crosscheck-only", action="store_true", help="run only the 30-qubit precision cross-check")
+    ap.add_argument("--config2-only", action="store_true", help="run only the config-2 pairwise microbenchmark")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM-counter calibration)")
     args = ap.parse_args()
@@ -647,6 +656,27 @@ def main():
 
     if args.crosscheck_only:
         print(json.dumps({"crosscheck_30q": crosscheck_30q(tnrcs, torch, np)}), flush=True)
+        return
+    if args.config2_only:
+        def timed(fn, n=5):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        res = config2_pairs(tnrcs, torch, timed)
+        if args.copy_probe_gib > 0:  # a plain device copy of known size (HBM-counter calibration)
+            n = int(args.copy_probe_gib * 2**30) // 8
+            src = torch.ones(n, dtype=torch.complex64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"config2": res}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch_uneven": batch_uneven(tnrcs, torch, np, args.batch_cap, "f16s")}), flush=True)
