@@ -16,7 +16,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
              "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "skew.hip", "gemm_c64.hip", "gemm_half.hip", "tune.hip", "probe.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "skew.hip", "splitk.hip", "gemm_c64.hip", "gemm_half.hip", "tune.hip", "probe.hip", "api.hip"]
 HOST_SOURCES = ["planner.cpp"]
 
 

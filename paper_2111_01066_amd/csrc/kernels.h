@@ -61,6 +61,12 @@ bool skew_ok(const IndexOp& op);
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s);
 int64_t splitk_blocks(const IndexOp& op);
+// split-K with both operands read in place (splitk_chunk_ok); *nblk = the
+// blocks whose partial sums it leaves in part
+hipError_t launch_splitk_chunk(int dtype, const void* A, const void* B, float2* part, const IndexOp& op,
+                               int64_t* nblk, hipStream_t s);
+// both operands hold their lowest k bits (up to 2^kSplitChunkLog2) lowest, in order
+bool splitk_chunk_aligned(const IndexOp& op);
 // The slice result is multiplied by d.root_scale, d.kappa0 and, if
 // sliced_factors, by the per-slice factor that the bind kernel left in ctrl.
 hipError_t launch_accum(int dtype, const void* root, const AccumDesc& d, Ctrl* ctrl, float* maxslots,

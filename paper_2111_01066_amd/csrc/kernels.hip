@@ -896,8 +896,18 @@ static Runs low_runs(const Runs& r, int bits) {
 }
 
 template <typename E>
-static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const IndexOp& op, float* maxslot,
-                            hipStream_t s) {
+static hipError_t launch_splitk_t(int dtype, const E* A, const E* B, E* C, float2* part, const IndexOp& op,
+                                  float* maxslot, hipStream_t s) {
+  // at most 8 x 8 outputs and an operand whose low k bits are not its low
+  // bits: both operands are read in place, chunk by chunk
+  if (splitk_chunk_ok(op.nM, op.nN, op.nK) && !splitk_chunk_aligned(op)) {
+    int64_t nb = 0;
+    const hipError_t e = launch_splitk_chunk(dtype, A, B, part, op, &nb, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_splitk_final<E>, dim3(1), dim3(256), 0, s, part, (int)nb, 1 << (op.nM + op.nN), C,
+                       op.out_scale, maxslot, op.nN, op.nN, op.nM, 0);
+    return hipSuccess;
+  }
   const int64_t g = splitk_blocks(op);
   // 16-byte runs of k when both operands hold their lowest k bits lowest
   constexpr int VK = 16 / (int)sizeof(E), LV = VK == 4 ? 2 : 1;
@@ -926,18 +936,20 @@ static void launch_splitk_t(const E* A, const E* B, E* C, float2* part, const In
     launch_splitk_v<1>(A, B, part, sub, gr, grid, s);
   hipLaunchKernelGGL(k_splitk_final<E>, dim3(groups), dim3(256), 0, s, part, (int)g, nout, C, op.out_scale, maxslot,
                      gn2, op.nN, gm, gr.gn_bits);
+  return hipSuccess;
 }
 
 hipError_t launch_splitk(int dtype, const void* A, const void* B, void* C, float2* part, const IndexOp& op,
                          float* maxslot, hipStream_t s) {
   if (op.nM + op.nN > kSplitKMaxOutLog2) return hipErrorInvalidValue;
+  hipError_t e;
   if (dtype == TN_DTYPE_F16S)
-    launch_splitk_t<cf16>((const cf16*)A, (const cf16*)B, (cf16*)C, part, op, maxslot, s);
+    e = launch_splitk_t<cf16>(dtype, (const cf16*)A, (const cf16*)B, (cf16*)C, part, op, maxslot, s);
   else if (dtype == TN_DTYPE_BF16S)
-    launch_splitk_t<cbf16>((const cbf16*)A, (const cbf16*)B, (cbf16*)C, part, op, maxslot, s);
+    e = launch_splitk_t<cbf16>(dtype, (const cbf16*)A, (const cbf16*)B, (cbf16*)C, part, op, maxslot, s);
   else
-    launch_splitk_t<float2>((const float2*)A, (const float2*)B, (float2*)C, part, op, maxslot, s);
-  return hipGetLastError();
+    e = launch_splitk_t<float2>(dtype, (const float2*)A, (const float2*)B, (float2*)C, part, op, maxslot, s);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ------------------------------------------------------------ accumulate --

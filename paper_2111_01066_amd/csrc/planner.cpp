@@ -771,17 +771,17 @@ int build_plan(PlanCore& P, std::string& err) {
       g.idx.nM = nM;
       g.idx.nN = nN;
       g.idx.nK = nK;
-      // split-K: consecutive threads take consecutive k, so an operand whose
-      // lowest k bits are not its lowest bits (in order) is gathered across
-      // the whole tensor; such an operand (of 2^12 entries or more) is first
-      // permuted to [free wires, K]
+      // split-K into more than 8 x 8 outputs: consecutive threads take
+      // consecutive k, so an operand whose lowest k bits are not its lowest
+      // bits (in order) is gathered across the whole tensor; such an operand
+      // (of 2^12 entries or more) is first permuted to [free wires, K]
       int tmp[2] = {-1, -1};
       std::vector<int> lay2[2] = {La, Lb};
       // the matrix-core skewed kernel with a long sum stages B chunk by
       // chunk: a B whose low k bits are scattered is permuted first too
       // (B only; A is read in place)
       const bool skew_long = cls == kOpSkew && nK >= 7;
-      if (splitk || skew_long) {
+      if ((splitk && !splitk_chunk_ok(nM, nN, nK)) || skew_long) {
         for (int side = skew_long ? 1 : 0; side < 2; ++side) {
           const std::vector<int>& have = side ? Lb : La;
           const int r = (int)have.size();

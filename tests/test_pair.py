@@ -63,10 +63,21 @@ TILED = [
     (list(range(7)), list(range(20, 27)), list(range(7)) + list(range(20, 27))),
     ([0, 500, 1, 2, 501, 3, 4, 5, 6, 7], [30, 500, 31, 32, 33, 501, 34, 35, 36], list(range(8)) + list(range(30, 37))),
 ]
-# split-K whose B holds the contracted wires in another order: B is first
-# permuted to [free wires, K] so that consecutive k are adjacent in memory
-ALIGN = [([20, 21, 22] + list(range(12)), [30, 31, 32] + [5, 0, 9, 2, 11, 7, 1, 4, 10, 3, 8, 6],
-          [20, 21, 22, 30, 31, 32])]
+# split-K into at most 8 x 8 outputs whose operands do not hold their
+# contracted wires lowest and in one order: both are read in place, chunk by
+# chunk (no permute).  B scattered; a free wire among A's low wires and B's
+# contracted wires in reverse order; no free wire on A's side; a sum of 2^20
+# terms (8 chunks per block) with both operands shuffled
+_SH = [int(x) for x in np.random.default_rng(7).permutation(20)]
+_SH2 = [int(x) for x in np.random.default_rng(8).permutation(20)]
+ALIGN = [
+    ([20, 21, 22] + list(range(12)), [30, 31, 32] + [5, 0, 9, 2, 11, 7, 1, 4, 10, 3, 8, 6],
+     [20, 21, 22, 30, 31, 32]),
+    ([50, 0, 1, 51, 2, 3, 4, 5, 6, 7, 8, 9, 52, 10, 11, 12, 13],
+     [13, 60, 11, 12, 9, 10, 61, 7, 8, 5, 6, 3, 4, 1, 2, 0], [50, 51, 52, 60, 61]),
+    ([3, 0, 8, 1, 9, 2, 10, 4, 11, 5, 12, 6, 7], [70, 71, 72] + list(range(13)), [70, 71, 72]),
+    ([80, 81] + _SH, [90] + _SH2[:10] + [91, 92] + _SH2[10:], [80, 81, 90, 91, 92]),
+]
 # dense with an A of 2^20+ entries whose contracted wires are not its lowest
 # block and at least 128 terms: the GEMM reads A in place (no permute of A);
 # K interleaved with M, K above M, K split around M in scattered order; A's
@@ -155,14 +166,14 @@ def test_pair_tiled_cases_plan_the_gathered_kernel(la, lb, lc):
 
 
 @pytest.mark.parametrize("la,lb,lc", ALIGN)
-def test_pair_splitk_aligns_scattered_operand(la, lb, lc):
-    pp = tnrcs.PairPlan(la, lb, lc, dry_run=True)
-    ops = pp.json()["ops"]
-    assert [o["kind"] for o in ops] == [0, 4]  # a permute of B, then split-K
-    assert ops[0]["a"] == [4, 0]  # the caller's B
-    run = ops[1]["bK"][0]
-    assert run[0] == 0 and run[1] == 0 and run[2] == 12  # all 12 k bits low and in order
-    pp.close()
+def test_pair_splitk_reads_scattered_operands_in_place(la, lb, lc):
+    for dt in ("c64", "f16s"):
+        pp = tnrcs.PairPlan(la, lb, lc, dry_run=True, dtype=dt)
+        ops = pp.json()["ops"]
+        sk = [o for o in ops if o["kind"] == 4]
+        assert len(sk) == 1 and sorted([sk[0]["a"], sk[0]["b"]]) == [[3, 0], [4, 0]]  # the caller's A and B
+        assert all(o["a"] not in ([3, 0], [4, 0]) for o in ops if o["kind"] == 0)  # neither is permuted
+        pp.close()
 
 
 @pytest.mark.parametrize("la,lb,lc", GATHER)
