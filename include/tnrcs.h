@@ -301,8 +301,8 @@ const char* tn_last_error(void);
  * carry integer labels (0..4095, most significant first; every dimension 2):
  * labels shared by A and B are contracted, and C's labels must be exactly
  * the unshared ones, in the caller's order.  The planner picks the same
- * kernels as for a network step (permute + MFMA GEMM, the skewed kernel,
- * or a gathered contraction) and adds a final permute when its natural
+ * kernels as for a network step (permute + MFMA GEMM, the skewed kernels,
+ * split-K or a gathered contraction) and adds a final permute when its natural
  * output order differs.  opts as for tn_plan (dtype, gemm_form, device;
  * host folding and graphs are not used).  Release with tn_plan_destroy. */
 int tn_pair_plan(int32_t rank_a, const int32_t* labels_a, int32_t rank_b, const int32_t* labels_b, int32_t rank_c,
