@@ -252,7 +252,8 @@ def config2_pairs(tnrcs, torch, timed, dtypes=("c64", "f16s")):
         out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
                                           "complex_rate_over_dtype_mfma_peak": tf / PEAK[dtype]}
         log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
-            f"TFLOP/s ({tf / PEAK[dtype]:.1%} of the {dtype} MFMA peak, permutes included)")
+            f"TFLOP/s at 8 flop per complex multiply-add, {tf / PEAK[dtype]:.2f}x the {dtype} dense MFMA peak "
+            f"(the 3M form issues 6), permutes included)")
         pp.close()
         del A, B, C
         torch.cuda.empty_cache()
