@@ -513,7 +513,7 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None, lanes: 
     different workspaces may run side by side).  Times every plan's slices
     launched plan by plan on one stream (each plan replaying its own
     per-slice graph), plan by plan on one stream per workspace, and the same
-    work as one batch graph launch (one branch per workspace); all must
+    work as one batch call (one lane per workspace); all must
     agree bitwise."""
     from rqcgen.workloads import config5, config5_table
     t = config5_table()
@@ -589,7 +589,7 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None, lanes: 
     flags = 0
     for p in plans:
         flags |= p.status()
-    log(f"[bench] batch: one graph launch {t_b:.3f} s ({flops / t_b / 1e12:.1f} complex TFLOP/s), graph built in "
+    log(f"[bench] batch: one batch call {t_b:.3f} s ({flops / t_b / 1e12:.1f} complex TFLOP/s), batch created in "
         f"{t_build:.2f} s, identical to plan-by-plan: {same}, flags {flags}")
     b.close()
     # where the batch time goes: every op of every plan timed alone (HIP
@@ -606,7 +606,7 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None, lanes: 
             busy += float(t_op) * n_sl[i] / 1e3
             if out_log2 < 20:
                 small += float(t_op) * n_sl[i] / 1e3
-    log(f"[bench] batch: kernels alone {busy:.3f} s ({busy / t_b:.1%} of the one-graph time), "
+    log(f"[bench] batch: kernels alone {busy:.3f} s ({busy / t_b:.1%} of the batch-call time), "
         f"{small:.3f} s of it in kernels with fewer than 2^20 outputs")
     for p in plans:
         p.close()
@@ -614,12 +614,12 @@ def batch_uneven(tnrcs, torch, np, cap: float, dtype: str, tune_db=None, lanes: 
     torch.cuda.empty_cache()
     return {"circuits": len(plans), "of": int(len(t["S"])), "max_order_flops": cap, "dtype": dtype,
             "workspaces": lanes, "plan_by_plan_streams_s": t_ml,
-            "kernel_time_s": busy, "kernel_time_over_one_graph": busy / t_b, "small_kernel_time_s": small,
+            "kernel_time_s": busy, "kernel_time_over_batch_call": busy / t_b, "small_kernel_time_s": small,
             "time_to_amplitudes_with_plan_s": t_plan + t_b,
             "slices": int(sum(n_sl)), "kernels": kernels, "flops": flops, "arena_bytes": int(need),
-            "plan_tune_calibrate_s": t_plan, "graph_build_s": t_build,
+            "plan_tune_calibrate_s": t_plan, "batch_create_s": t_build,
             "plan_by_plan_s": t_seq, "plan_by_plan_complex_tflops": flops / t_seq / 1e12,
-            "one_graph_s": t_b, "one_graph_complex_tflops": flops / t_b / 1e12, "speedup": t_seq / t_b,
+            "batch_call_s": t_b, "batch_call_complex_tflops": flops / t_b / 1e12, "speedup": t_seq / t_b,
             "bitwise_identical": same, "numeric_flags": flags}
 
 

@@ -214,15 +214,15 @@ int tn_contract_slices_checked(tn_plan_t p, int64_t s_begin, int64_t s_end, void
  * without an output shift (a permute) or an index out of range. */
 int tn_plan_shift_outputs(tn_plan_t p, int32_t op, int32_t delta);
 
-/* ---- batches of plans (many circuits in one launch) ----
+/* ---- batches of plans (many circuits in one call) ----
  * An extension with no counterpart in the paper: slices of several
- * independent networks (different circuits) run as one captured launch.  Each
- * network's value is still the sum over its slices (main text,
- * customized-TNC section). */
+ * independent networks (different circuits) run from one call, in lanes
+ * that may run side by side.  Each network's value is still the sum over its
+ * slices (main text, customized-TNC section). */
 
 typedef struct tn_batch_s* tn_batch_t;
 
-/* Captures, once, the graphs that run plans[0..n): for plan i the
+/* Prepares a batch that runs plans[0..n): for plan i the
  * slices ranges[2i] <= s < ranges[2i+1], accumulated (+=) into amps[i]
  * (device complex128[2^n_open of plan i]) exactly as tn_contract_slices
  * would (same kernels, same order, same sums).  Plans may be of different
@@ -230,20 +230,22 @@ typedef struct tn_batch_s* tn_batch_t;
  * (opts.arena); the same plan may appear more than once.  Plans whose
  * arenas overlap, that are the same plan or that share an amplitude buffer
  * run one after the other, in the order given, in one lane; plans on
- * separate arenas may go to separate lanes (at most 4).  Each lane is one
- * captured HIP graph; lanes other than the first run on streams of the
- * batch (default priority) that start after the caller's stream's earlier
- * work and that the caller's stream waits for, so lanes run side by side.
- * The plans and amplitude buffers must outlive the batch, and a plan must
- * not be run elsewhere while the batch runs.  Node count: the sum over plans of (slices x
- * (kernels per slice)) plus one per plan. */
+ * separate arenas may go to separate lanes (at most 4).  In a lane, each
+ * plan sets its slice cursor and replays its per-slice HIP graph (captured
+ * here for every plan with opts.use_graph) once per slice.  Each lane runs
+ * on a stream of the batch (default priority) that starts after the
+ * caller's stream's earlier work and that the caller's stream waits for, so
+ * lanes run side by side.  The plans and amplitude buffers must
+ * outlive the batch, and a plan must not be run elsewhere while the batch
+ * runs. */
 int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, void* const* amps, tn_batch_t* out);
 
-/* Enqueues the batch on `stream`: one graph launch per lane, the lanes
+/* Enqueues the batch on `stream`: every lane's plans in order, the lanes
  * joined back into `stream`.  Asynchronous. */
 int tn_batch_run(tn_batch_t b, void* stream);
 
-/* Releases the batch's graphs and streams (not the plans).  NULL is accepted. */
+/* Releases the batch's streams and events (not the plans or their graphs).
+ * NULL is accepted. */
 int tn_batch_destroy(tn_batch_t b);
 
 /* One-shot form: tn_batch_create, tn_batch_run on `stream`, wait for the

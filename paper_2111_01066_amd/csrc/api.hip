@@ -121,33 +121,24 @@ constexpr int kBatchMaxLanes = 4;
 // not overlap.)
 struct tn_batch_s {
   int device = 0;
-  int64_t nodes = 0;
   std::vector<tn_plan_s*> plans;
-  hipStream_t cap_stream = nullptr;
-  std::vector<hipGraph_t> graphs;
-  std::vector<hipGraphExec_t> execs;
-  std::vector<hipStream_t> lane_streams;  // lane k >= 1 (lane 0 runs on the caller's stream)
-  std::vector<hipEvent_t> fork, join;     // fork[k] / join[k] for lane k >= 1
+  std::vector<int64_t> ranges;            // [begin, end) of plan i at 2i, 2i + 1
+  std::vector<void*> amps;
+  std::vector<std::vector<int>> lanes;    // plan indices of each lane, in the order given
+  std::vector<hipStream_t> lane_streams;  // one per lane
+  std::vector<hipEvent_t> fork, join;     // fork[k] / join[k] for lane k
 };
 
 static void batch_release(tn_batch_s* b) {
-  for (hipGraphExec_t x : b->execs)
-    if (x) hipGraphExecDestroy(x);
-  for (hipGraph_t g : b->graphs)
-    if (g) hipGraphDestroy(g);
   for (hipStream_t st : b->lane_streams)
     if (st) hipStreamDestroy(st);
   for (hipEvent_t ev : b->fork)
     if (ev) hipEventDestroy(ev);
   for (hipEvent_t ev : b->join)
     if (ev) hipEventDestroy(ev);
-  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-  b->execs.clear();
-  b->graphs.clear();
   b->lane_streams.clear();
   b->fork.clear();
   b->join.clear();
-  b->cap_stream = nullptr;
 }
 
 static char* resolve(const tn_plan_s* p, const TRef& r) {
@@ -797,22 +788,27 @@ int tn_pair_run(tn_plan_t p, const void* A, const void* B, void* C, int64_t batc
 
 // Runs `count` slices from the cursor on, replaying the per-slice graph
 // (captured on first use) or enqueueing the kernels directly.
+// Captures the plan's per-slice graph once (plans with opts.use_graph).
+static int ensure_graph(tn_plan_s* p) {
+  if (!p->core.opts.use_graph || p->exec) return TN_OK;
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "create capture stream");
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  int rc = enqueue_slice(p, p->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  p->graph = g;
+  HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate graph");
+  return TN_OK;
+}
+
 static int run_slices(tn_plan_s* p, int64_t count, hipStream_t s) {
   if (p->core.opts.use_graph) {
-    if (!p->exec) {
-      if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "create capture stream");
-      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-      int rc = enqueue_slice(p, p->cap_stream);
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
-      if (rc) {
-        if (g) hipGraphDestroy(g);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(e, "end capture");
-      p->graph = g;
-      HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate graph");
-    }
+    if (int rc = ensure_graph(p)) return rc;
     for (int64_t i = 0; i < count; ++i) HIP_TRY(hipGraphLaunch(p->exec, s), "graph launch");
   } else {
     for (int64_t i = 0; i < count; ++i) {
@@ -928,7 +924,7 @@ int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, vo
   *out = nullptr;
   if (n < 0 || (n > 0 && (!plans || !ranges || !amps))) return fail(TN_E_ARG, "bad batch lists");
   int device = -1;
-  int64_t nodes = 0;
+  bool work = false;
   for (int i = 0; i < n; ++i) {
     const tn_plan_s* p = plans[i];
     const std::string at = "batch entry " + std::to_string(i) + ": ";
@@ -941,14 +937,15 @@ int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, vo
     if (b < 0 || e < b || e > p->core.stats.n_slices)
       return fail(TN_E_ARG, at + "slice range outside [0, " + std::to_string(p->core.stats.n_slices) + ")");
     if (e > b && !amps[i]) return fail(TN_E_ARG, at + "amp is NULL");
-    nodes += (e - b) * (int64_t)(p->core.stats.n_kernels + 1);
+    work |= e > b;
   }
   tn_batch_s* b = new (std::nothrow) tn_batch_s();
   if (!b) return fail(TN_E_MEM, "host allocation failed");
   b->plans.assign(plans, plans + n);
+  b->ranges.assign(ranges, ranges + 2 * (int64_t)n);
+  b->amps.assign(amps, amps + n);
   b->device = device < 0 ? 0 : device;
-  b->nodes = nodes;
-  if (nodes == 0) {
+  if (!work) {
     *out = b;
     return TN_OK;
   }
@@ -984,40 +981,21 @@ int tn_batch_create(const tn_plan_t* plans, int32_t n, const int64_t* ranges, vo
     lane_of[i] = id;
   }
   const int n_lanes = std::max<int>(1, std::min<int>((int)first_of.size(), kBatchMaxLanes));
-  for (int i = 0; i < n; ++i) lane_of[i] %= n_lanes;
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
-  if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
-    return bail(hip_fail(e, "create capture stream"));
   for (int k = 0; k < n_lanes; ++k) {
     std::vector<int> mine;
     for (int i = 0; i < n; ++i)
-      if (lane_of[i] == k && ranges[2 * i + 1] > ranges[2 * i]) mine.push_back(i);
-    if (mine.empty()) continue;
-    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return bail(hip_fail(e, "begin capture"));
-    int rc = TN_OK;
-    for (int i : mine) {
-      if (rc) break;
-      tn_plan_s* p = plans[i];
-      const int64_t s0 = ranges[2 * i], s1 = ranges[2 * i + 1];
-      hipError_t e2 = launch_set_ctrl(p->d_ctrl, s0, amps[i], b->cap_stream);
-      if (e2 != hipSuccess) rc = hip_fail(e2, "control kernel");
-      for (int64_t sl = s0; sl < s1 && rc == TN_OK; ++sl) rc = enqueue_slice(p, b->cap_stream);
-    }
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->cap_stream, &g);
-    if (g) b->graphs.push_back(g);
-    if (rc) return bail(rc);
-    if (e != hipSuccess) return bail(hip_fail(e, "end capture"));
-    hipGraphExec_t x = nullptr;
-    if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
-      return bail(hip_fail(e, "instantiate batch graph"));
-    b->execs.push_back(x);
+      if (lane_of[i] % n_lanes == k && ranges[2 * i + 1] > ranges[2 * i]) mine.push_back(i);
+    if (!mine.empty()) b->lanes.push_back(mine);
   }
-  hipStreamDestroy(b->cap_stream);
-  b->cap_stream = nullptr;
-  for (size_t k = 1; k < b->execs.size(); ++k) {
+  // every plan's per-slice graph is captured now, so that a run only replays
+  for (int i = 0; i < n; ++i)
+    if (ranges[2 * i + 1] > ranges[2 * i])
+      if (int rc = ensure_graph(plans[i])) return bail(rc);
+  // each lane gets a stream of its own, created one after the other so that
+  // the runtime spreads them over its hardware queues
+  for (size_t k = 0; k < b->lanes.size(); ++k) {
     hipStream_t st = nullptr;
     hipEvent_t f = nullptr, j = nullptr;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) == hipSuccess) b->lane_streams.push_back(st);
@@ -1038,18 +1016,32 @@ int tn_batch_run(tn_batch_t b, void* stream) {
     p->last_stream = s;
     p->ran = true;
   }
-  if (b->execs.empty()) return TN_OK;
+  if (b->lanes.empty()) return TN_OK;
   HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
-  // lanes 1.. start after the work already on the caller's stream, lane 0
-  // runs on it, and the caller's stream then waits for every lane
-  for (size_t k = 1; k < b->execs.size(); ++k) {
-    HIP_TRY(hipEventRecord(b->fork[k - 1], s), "batch fork");
-    HIP_TRY(hipStreamWaitEvent(b->lane_streams[k - 1], b->fork[k - 1], 0), "batch fork");
-    HIP_TRY(hipGraphLaunch(b->execs[k], b->lane_streams[k - 1]), "batch graph launch");
-    HIP_TRY(hipEventRecord(b->join[k - 1], b->lane_streams[k - 1]), "batch join");
+  // the lanes start after the work already on the caller's stream, and the
+  // caller's stream then waits for every lane; in a lane, each plan sets its
+  // slice cursor and replays its per-slice graph
+  for (size_t k = 0; k < b->lanes.size(); ++k) {
+    HIP_TRY(hipEventRecord(b->fork[k], s), "batch fork");
+    HIP_TRY(hipStreamWaitEvent(b->lane_streams[k], b->fork[k], 0), "batch fork");
   }
-  HIP_TRY(hipGraphLaunch(b->execs[0], s), "batch graph launch");
-  for (size_t k = 1; k < b->execs.size(); ++k) HIP_TRY(hipStreamWaitEvent(s, b->join[k - 1], 0), "batch join");
+  // plans are issued to the lanes in turn (the j-th plan of every lane, then
+  // the (j+1)-th), so that every lane has work queued from the start
+  size_t longest = 0;
+  for (const std::vector<int>& l : b->lanes) longest = std::max(longest, l.size());
+  for (size_t j = 0; j < longest; ++j)
+    for (size_t k = 0; k < b->lanes.size(); ++k) {
+      if (j >= b->lanes[k].size()) continue;
+      const int i = b->lanes[k][j];
+      tn_plan_s* p = b->plans[i];
+      const int64_t s0 = b->ranges[2 * i], s1 = b->ranges[2 * i + 1];
+      HIP_TRY(launch_set_ctrl(p->d_ctrl, s0, b->amps[i], b->lane_streams[k]), "control kernel");
+      if (int rc = run_slices(p, s1 - s0, b->lane_streams[k])) return rc;
+    }
+  for (size_t k = 0; k < b->lanes.size(); ++k) {
+    HIP_TRY(hipEventRecord(b->join[k], b->lane_streams[k]), "batch join");
+    HIP_TRY(hipStreamWaitEvent(s, b->join[k], 0), "batch join");
+  }
   return TN_OK;
 }
 

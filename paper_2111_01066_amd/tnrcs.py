@@ -280,8 +280,9 @@ class Plan:
 
 
 class Batch:
-    """Owns a tn_batch_t: one captured HIP graph that runs plans[i] over the
-    slice range ranges[i] into amps[i], for all i, in list order."""
+    """Owns a tn_batch_t that runs plans[i] over the slice range ranges[i]
+    into amps[i], for all i (in list order within a lane of plans that share
+    an arena workspace)."""
 
     def __init__(self, plans: Sequence[Plan], ranges: Sequence, amps: Sequence):
         self._h = None
@@ -311,7 +312,7 @@ class Batch:
 
 
 def tn_contract_batch(plans: Sequence[Plan], ranges: Sequence, amps: Sequence, stream=None):
-    """One-shot batch: capture, launch, wait, release."""
+    """One-shot batch: create, run, wait, release."""
     n = len(plans)
     hp = (c_void_p * max(1, n))(*[p._h for p in plans])
     rg = (c_int64 * max(1, 2 * n))(*[int(x) for r in ranges for x in r])
