@@ -8,8 +8,9 @@
 // bits that sit at the lowest positions of A and of B, so one chunk of A
 // (2^nM rows x 256 k) and one of B are each a set of runs of consecutive
 // addresses.  Each is loaded in address order (the chunk map of the skewed
-// kernels) in 16-byte loads and staged in LDS as planar FP32 rows; thread t
-// then multiplies chunk entry k = t into its 2^nM x 2^nN accumulators.
+// kernels) in loads of up to 16 bytes and staged in LDS as planar FP32 rows;
+// thread t then multiplies chunk entry k = t into its 2^nM x 2^nN
+// accumulators.
 // Block b takes the chunks b, b + G, b + 2G, ... (G = gridDim.x, a power of
 // two): from one to the next the bits lg .. lg + ctz(i + 1) of the chunk
 // index flip (lg = log2 G), so the chunk's offsets in A and B move by one XOR
