@@ -251,7 +251,7 @@ inline bool gemm_gather_ok(const IndexOp& idx) {
 // whatever their layout (chunks of 2^kSplitChunkLog2 k loaded in address
 // order), so the planner permutes neither operand for them.
 constexpr int kSplitChunkLog2 = 8;
-inline bool splitk_chunk_ok(int nM, int nN, int nK) { return nM <= 3 && nN <= 3 && nK >= 12; }
+inline bool splitk_chunk_ok(int nM, int nN, int nK) { return nM <= 3 && nN <= 3 && nK >= 12 && nK <= 40; }
 // Planner entry (host only).  Returns TN_OK or an error code with a message.
 int build_plan(PlanCore& P, std::string& err);
 // Blocks of the split-K reduction over 2^nK terms (its workspace holds

@@ -254,7 +254,7 @@ bool splitk_chunk_aligned(const IndexOp& op) {
 
 hipError_t launch_splitk_chunk(int dtype, const void* A, const void* B, float2* part, const IndexOp& op,
                                int64_t* nblk, hipStream_t s) {
-  if (!splitk_chunk_ok(op.nM, op.nN, op.nK) || op.nK > 40) return hipErrorInvalidValue;
+  if (!splitk_chunk_ok(op.nM, op.nN, op.nK)) return hipErrorInvalidValue;
   const int nK = op.nK;
   std::vector<int> pa(nK), pb(nK);
   for (int j = 0; j < nK; ++j) {
