@@ -183,12 +183,14 @@ def roofline(by_kind, dtype, copy_gbs=None):
     if dom == 1:
         achieved = d["issued"] / d["n"] / (avg_ms / 1e3) / 1e12
         return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK[dtype], "unit": "TFLOP/s",
-                "frac": achieved / PEAK[dtype], "traffic": measured_traffic(name, dtype),
+                "frac": achieved / PEAK[dtype], "traffic": measured_traffic(name, dtype, d["bytes"] / d["n"]),
                 "launches_per_slice": d["n"], "avg_ms": avg_ms, "flop_per_launch": d["issued"] / d["n"],
+                "bytes_per_launch": d["bytes"] / d["n"],
                 "complex_tflops": d["flops"] / d["n"] / (avg_ms / 1e3) / 1e12,
                 "note": "achieved = issued real MFMA flops per launch (6 per complex multiply-add in the 3M form, "
-                        "8 in 4M) / mean launch duration (HIP events on the launch stream); traffic = HBM bytes "
-                        "per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain copy)"}
+                        "8 in 4M) / mean launch duration (HIP events on the launch stream); traffic = this run's "
+                        "algorithmic bytes per launch x the HBM/algorithmic ratio that rocprofv3 FETCH_SIZE + "
+                        "WRITE_SIZE (scaled by a plain copy) measured on the same kernels (profiles/traffic.json)"}
     achieved = d["bytes"] / d["n"] / (avg_ms / 1e3) / 1e9
     r = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
          "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name, dtype, d["bytes"] / d["n"]),
@@ -252,8 +254,8 @@ def config2_pairs(tnrcs, torch, timed, dtypes=("c64", "f16s")):
         out[f"pairs_rank27x25_{dtype}"] = {"ms_per_launch": ms, "complex_tflops": tf, "pairs_per_launch": n_pairs,
                                           "complex_rate_over_dtype_mfma_peak": tf / PEAK[dtype]}
         log(f"[bench] config 2 ({n_pairs} rank-27 x rank-25 pairs) {dtype}: {ms:.1f} ms/launch, {tf:.1f} complex "
-            f"TFLOP/s at 8 flop per complex multiply-add, {tf / PEAK[dtype]:.2f}x the {dtype} dense MFMA peak "
-            f"(the 3M form issues 6), permutes included)")
+            f"TFLOP/s at 8 flop per complex multiply-add, {tf / PEAK[dtype]:.2f}x the {dtype} dense MFMA peak"
+            f"{' (the 3M form issues 6)' if dtype == 'c64' else ''}, permutes included)")
         pp.close()
         del A, B, C
         torch.cuda.empty_cache()
