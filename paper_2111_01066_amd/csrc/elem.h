@@ -47,6 +47,19 @@ __device__ __forceinline__ uint64_t dep(uint64_t x, const Runs& r) {
   return o;
 }
 
+// The same with the first N runs unrolled: their fields are read at fixed
+// offsets of the kernel argument (scalar loads) instead of at a run index
+// (a vector load per field), for maps evaluated once per output tile.
+template <int N>
+__device__ __forceinline__ uint64_t dep_u(uint64_t x, const Runs& r) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < r.n) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
+  for (int i = N; i < r.n; ++i) o |= ((x >> r.src[i]) & ((1ull << r.len[i]) - 1ull)) << r.dst[i];
+  return o;
+}
+
 // Running maximum of |re|, |im| for the range check of scaled storage; a
 // NaN counts as +inf (it comes from an overflow earlier in the same sum).
 __device__ __forceinline__ float mag_max(float m, float re, float im) {

@@ -41,16 +41,21 @@ __device__ __forceinline__ int skew_h(const SkewMap& mp, int m, int k) {
 }
 
 // Chunk element e -> its offset from the chunk's first entry, its row m and
-// its k within the chunk.
+// its k within the chunk.  Unrolled over the largest map, so that the map's
+// fields are read at fixed offsets of the kernel argument (scalar loads): the
+// GEMMs that read A in place evaluate it in every workgroup, one per tile.
 __device__ __forceinline__ void skew_split(const SkewMap& mp, int e, uint64_t& off, int& m, int& k) {
   off = 0;
   m = 0;
   k = 0;
-  for (int i = 0; i < mp.v; ++i) {
-    const int b = (e >> i) & 1;
-    off |= (uint64_t)b << mp.pos[i];
-    if (mp.mb[i] >= 0) m |= b << mp.mb[i];
-    if (mp.kb[i] >= 0) k |= b << mp.kb[i];
+#pragma unroll
+  for (int i = 0; i < kSkewMaxV; ++i) {
+    if (i < mp.v) {
+      const int b = (e >> i) & 1;
+      off |= (uint64_t)b << mp.pos[i];
+      if (mp.mb[i] >= 0) m |= b << mp.mb[i];
+      if (mp.kb[i] >= 0) k |= b << mp.kb[i];
+    }
   }
 }
 

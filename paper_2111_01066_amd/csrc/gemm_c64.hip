@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm128(const float2* __restrict__ 
       eoff[j] = (uint32_t)off;
       eidx[j] = (uint32_t)(k0 * LD + m0) | ((uint32_t)(k1 * LD + m1) << 16);
     }
-    abase = dep((uint64_t)bm, g.aM);
+    abase = dep_u<12>((uint64_t)bm, g.aM);
   }
   auto load_a = [&]() {
     if constexpr (GA != 0) {

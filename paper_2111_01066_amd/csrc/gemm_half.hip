@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256, 2) void k_hgemm_ga(const E* __restrict__ A, co
     eoff[j] = (uint32_t)off;
     lidx[j] = m * LDK + k;
   }
-  const uint64_t abase = dep((uint64_t)bm, g.aM);
+  const uint64_t abase = dep_u<12>((uint64_t)bm, g.aM);
   uint64_t kofs = 0;
   const int brow = tid / 2, bk = (tid % 2) * 16;
   const uint4* Bp = reinterpret_cast<const uint4*>(B + (bn + brow) * K + bk);
