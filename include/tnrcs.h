@@ -152,7 +152,7 @@ typedef struct {
  * valid tile size, K-split count and kernel variant is timed with HIP events
  * on the plan's own buffers (the arena is filled with random values first:
  * the matrix cores run faster on zeros) and the fastest kept.  Dense steps
- * that read a large A in place (no permute of A; at least 2^7 terms and,
+ * that read a large A in place (no permute of A; at least 2^5 terms and,
  * for sums of 2^11 terms or more, at least 512 output tiles of 128x128)
  * have one fixed kernel and are not timed.
  * Results are cached per process and, with tune_db, in a file (lines

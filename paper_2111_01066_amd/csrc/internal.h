@@ -232,7 +232,7 @@ inline int run_pos(const Runs& r, int j) {
 // 512 output tiles when the sum has 2^11 terms or more, since the in-place
 // kernels do not split K.)
 constexpr int kGatherMinLog2 = 20;
-constexpr int kGatherMinK = 7;
+constexpr int kGatherMinK = 5;
 inline bool gemm_gather_ok(const IndexOp& idx) {
   if (idx.nM < 7 || idx.nN < 7 || idx.nK < 4) return false;
   for (int j = 0; j < 7; ++j) {

@@ -642,10 +642,9 @@ int build_plan(PlanCore& P, std::string& err) {
       std::vector<int> Kord;
       if (!k_low_block(La, Kord) && !k_low_block(Lb, Kord)) Kord = K;
       // a large A that would need a permute is read in place by the GEMM,
-      // with the K bits in A's own order (B is permuted to match).  Only for
-      // K >= 128: on shorter sums the in-place GEMM (128x128 tiles only)
-      // measured slower than the permute plus the tuned GEMM.  Scaled
-      // storage uses the 4M form there.
+      // with the K bits in A's own order (B is permuted to match), for sums
+      // of 2^kGatherMinK terms or more.  Scaled storage uses the 4M form
+      // there.
       IndexOp gidx;
       bool gather = false;
       {

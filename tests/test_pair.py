@@ -79,7 +79,7 @@ ALIGN = [
     ([80, 81] + _SH, [90] + _SH2[:10] + [91, 92] + _SH2[10:], [80, 81, 90, 91, 92]),
 ]
 # dense with an A of 2^20+ entries whose contracted wires are not its lowest
-# block and at least 128 terms: the GEMM reads A in place (no permute of A);
+# block and at least 32 terms: the GEMM reads A in place (no permute of A);
 # K interleaved with M, K above M, K split around M in scattered order; A's
 # two lowest wires are (row, k), (row, row), (k, k) and (k, row), the four
 # ways the 16-bit kernel deinterleaves a 16-byte load
@@ -94,6 +94,9 @@ GATHER = [
      list(range(740, 748)) + [4, 3, 5, 2, 6, 1, 7, 0, 8], list(range(640, 652)) + list(range(740, 748))),
     ([0, 1, 2, 3, 4] + list(range(660, 673)) + [5, 673, 6], [6, 5, 4, 3, 2, 1, 0] + list(range(760, 767)),
      list(range(660, 674)) + list(range(760, 767))),
+    # the shortest sum read in place: 32 terms
+    ([680, 681, 0, 682, 683, 1, 684, 685, 2, 686, 687, 3] + list(range(688, 695)) + [4],
+     list(range(780, 787)) + [4, 3, 2, 1, 0], list(range(680, 695)) + list(range(780, 787))),
 ]
 # long sums into more than 64 outputs: split-K over groups of 64 outputs
 # (512 and 2048 outputs; one operand's contracted wires scattered), and a
