@@ -4,17 +4,19 @@ out of any oracle's reach in this suite, but slicing is an exact identity
 (main text, customized-TNC section: the network is the sum over the values
 of its sliced wires):
 
-* slices 0 and one seeded slice of the benchmark plan (intermediates of up to
-  2^32 entries), computed by the plan exactly as the benchmark runs it (with
-  the autotuner) and with the default kernel rules, match the fixture
-  tests/golden/config3_slices.txt that the oracle alone wrote as sums of
-  sub-slices (complex64 1e-5, scaled FP16 1e-2, scaled BF16 6e-2, normwise);
-* one seeded sub-slice (more wires sliced until every tensor has at most
-  2^29 entries), computed by the GPU through a plan over the extended sliced
-  set, matches the oracle's FP64 contraction of the same sub-slice, computed
-  here;
-* slice 0 of the benchmark plan equals the sum of its sub-slices computed by
-  the extended plan, within 1e-5 of the sum's norm."""
+* the slices that the fixture tests/golden/config3_slices.txt holds (slice 0,
+  and the seeded slice once its oracle run has finished), computed by the
+  benchmark plan (intermediates of up to 2^32 entries) exactly as the
+  benchmark runs it (with the autotuner) and with the default kernel rules,
+  match the fixture, which the oracle alone wrote as sums of sub-slices
+  (complex64 1e-5, scaled FP16 1e-2, scaled BF16 6e-2, normwise);
+* for slice 0 and for the seeded slice: one seeded sub-slice (more wires
+  sliced until every tensor has at most 2^29 entries), computed by the GPU
+  through a plan over the extended sliced set, matches the oracle's FP64
+  contraction of the same sub-slice, computed here;
+* slice 0 and the seeded slice of the benchmark plan each equal the sum of
+  their sub-slices computed by the extended plan, within 1e-5 of the sum's
+  norm."""
 import os
 
 import numpy as np
@@ -67,19 +69,20 @@ def test_config3_slices_vs_oracle_fixture(work, fixture_amps, dtype, tune):
     assert flags & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
 
 
-@pytest.fixture(scope="module")
-def sub(work):
+@pytest.fixture(scope="module", params=["slice0", "seeded"])
+def sub(work, request):
     w = work
     ns = network_structure(w.circuit, w.open_qubits)
     allsl = slice_to_fit(ns, w.pairs, SUB_LOG2, initial=w.sliced)
     k = len(w.sliced)
     assert list(allsl[:k]) == list(w.sliced) and len(allsl) > k
+    s = 0 if request.param == "slice0" else golden.seeded_slice(k)
     e = int(np.random.default_rng(7).integers(1 << (len(allsl) - k)))
-    s_ext = e << k  # slice 0 of the benchmark slicing, extra wires set to the bits of e
-    print(f"config 3: oracle sub-slice {e} of slice 0 ({len(allsl) - k} extra wires)", flush=True)
+    s_ext = s | (e << k)  # slice s of the benchmark slicing, extra wires set to the bits of e
+    print(f"config 3: oracle sub-slice {e} of slice {s} ({len(allsl) - k} extra wires)", flush=True)
     leaves, ow = oracle.build_network(w.circuit, w.open_qubits, w.out_bits)
     ref = contract_network(leaves, w.pairs, ow, slice_assignment(allsl, s_ext))
-    return {"allsl": allsl, "k": k, "s_ext": s_ext, "ref": ref}
+    return {"allsl": allsl, "k": k, "s": s, "s_ext": s_ext, "ref": ref}
 
 
 @pytest.mark.parametrize("dtype", ["c64", "f16s", "bf16s"])
@@ -99,14 +102,14 @@ def test_config3_subslice_vs_oracle(work, sub, dtype):
     assert err < TOL[dtype]
 
 
-def test_config3_slice0_is_sum_of_subslices(work, sub):
-    w, k = work, sub["k"]
+def test_config3_slice_is_sum_of_subslices(work, sub):
+    w, k, s = work, sub["k"], sub["s"]
     n_sub = 1 << (len(sub["allsl"]) - k)
-    print(f"config 3 slice 0 against the sum of its {n_sub} sub-slices, c64", flush=True)
+    print(f"config 3 slice {s} against the sum of its {n_sub} sub-slices, c64", flush=True)
     ext = tnrcs.Plan(w.circuit, w.pairs, sub["allsl"], w.open_qubits, w.out_bits)
     parts = torch.zeros(n_sub, 64, dtype=torch.complex128, device="cuda")
     for e in range(n_sub):
-        ext.contract(e << k, (e << k) + 1, parts[e])
+        ext.contract(s | (e << k), (s | (e << k)) + 1, parts[e])
     torch.cuda.synchronize()
     parts = parts.cpu().numpy()
     want = parts.sum(axis=0)
@@ -115,7 +118,7 @@ def test_config3_slice0_is_sum_of_subslices(work, sub):
     plan = tnrcs.Plan(w.circuit, w.pairs, w.sliced, w.open_qubits, w.out_bits)
     assert plan.info()["max_log2"] == 32
     amp = torch.zeros(64, dtype=torch.complex128, device="cuda")
-    plan.contract(0, 1, amp)
+    plan.contract(s, s + 1, amp)
     torch.cuda.synchronize()
     assert plan.status() & (tnrcs.FLAG_NONFINITE | tnrcs.FLAG_OVERFLOW) == 0
     plan.close()
